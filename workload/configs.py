@@ -1,0 +1,69 @@
+"""Named synthetic workloads.
+
+Seeds are numpy.random.default_rng(250700156 + k) for workload k; draw order: density coefficients,
+then the near-target base directions, then the signed distances b.
+
+  c1      unit sphere, h = 1/16 (N = 4302); densities: degree <= 3 harmonics; targets: all quadrature
+          points + 1000 near points with b ~ U[-3h, 3h]; rho = (2, 3, 4).
+  c2      ellipsoid (1, 0.8, 0.6), h = 1/64 (N = 42342); degree <= 4; targets: all quadrature points
+          + 20000 near points within +-3h (M = 62342).
+  c3      ellipsoid (1, 0.8, 0.6), h = 1/128 (N = 169342); as c2 (M = 189342).
+  table1  spheroid x1^2 + 4 x2^2 + 4 x3^2 = 1 at h (Table 1 of the paper): targets are the grid points
+          within h outside; density f1 = 1/sqrt(1 - 3 x1^2 / 4), f2 = f3 = 0; rho = (3, 4, 5).
+  small   ellipsoid (1, 0.8, 0.6), h = 1/24 (N ~ 6e3), degree <= 4, 800 near targets: a parity case
+          that spans many tiles and a ragged tail at a size the oracle finishes in seconds.
+
+The double-layer density q is the same field as f (q = f).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .surface import ellipsoid_quadrature
+from .targets import concat_targets, grid_targets_outside, near_targets, on_surface_targets
+from .density import harmonic_coeffs, harmonic_field
+
+SEED_BASE = 250700156
+
+CONFIGS = {
+    "c1": dict(k=1, axes=(1.0, 1.0, 1.0), h=1 / 16, L=3, m_near=1000, bmax_h=3.0, rho=(2.0, 3.0, 4.0)),
+    "c2": dict(k=2, axes=(1.0, 0.8, 0.6), h=1 / 64, L=4, m_near=20000, bmax_h=3.0, rho=(2.0, 3.0, 4.0)),
+    "c3": dict(k=3, axes=(1.0, 0.8, 0.6), h=1 / 128, L=4, m_near=20000, bmax_h=3.0, rho=(2.0, 3.0, 4.0)),
+    "small": dict(k=11, axes=(1.0, 0.8, 0.6), h=1 / 24, L=4, m_near=800, bmax_h=3.0, rho=(2.0, 3.0, 4.0)),
+    "tiny": dict(k=12, axes=(1.0, 0.8, 0.6), h=1 / 10, L=2, m_near=100, bmax_h=3.0, rho=(2.0, 3.0, 4.0)),
+}
+
+
+def build_config(name: str, h: float | None = None, m_near: int | None = None, seed_offset: int = 0) -> dict:
+    """Return a dict: surf, targets, f, f0, q, q0, h, rho (and the generator parameters)."""
+    if name.startswith("table1"):
+        hh = h if h is not None else 1 / 32
+        axes = (1.0, 0.5, 0.5)
+        surf = ellipsoid_quadrature(axes, hh)
+        t = grid_targets_outside(axes, hh)
+
+        def fld(x):
+            out = np.zeros_like(x)
+            out[:, 0] = 1.0 / np.sqrt(1.0 - 0.75 * np.clip(x[:, 0], -1, 1) ** 2)
+            return out
+
+        f = fld(surf.x)
+        f0 = fld(t.x0)
+        return dict(name=name, surf=surf, targets=t, f=f, f0=f0, q=f.copy(), q0=f0.copy(), h=hh,
+                    rho=(3.0, 4.0, 5.0), axes=axes)
+    cfg = dict(CONFIGS[name])
+    if h is not None:
+        cfg["h"] = h
+    if m_near is not None:
+        cfg["m_near"] = m_near
+    rng = np.random.default_rng(SEED_BASE + cfg["k"] + seed_offset)
+    coeffs = harmonic_coeffs(cfg["L"], rng)
+    surf = ellipsoid_quadrature(cfg["axes"], cfg["h"])
+    t_on = on_surface_targets(surf)
+    t_near = near_targets(cfg["axes"], cfg["m_near"], cfg["bmax_h"] * cfg["h"], rng)
+    t = concat_targets(t_on, t_near)
+    f = harmonic_field(coeffs, surf.x)
+    f0 = harmonic_field(coeffs, t.x0)
+    f0[: surf.n] = f  # on-surface targets: density at x0 is exactly the source value
+    return dict(name=name, surf=surf, targets=t, f=f, f0=f0, q=f.copy(), q0=f0.copy(), h=cfg["h"],
+                rho=tuple(cfg["rho"]), axes=cfg["axes"], coeffs=coeffs)
