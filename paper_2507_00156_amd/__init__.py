@@ -1,0 +1,16 @@
+"""Extrapolated-regularization Stokes single/double-layer sums on MI355X (gfx950).
+
+The compute path is libstokesreg.so (hand-written HIP kernels behind the C ABI of
+include/stokesreg.h); `binding` marshals torch tensors into it and `Evaluator` is a small
+convenience wrapper.  Nothing here computes the method on the CPU.
+"""
+from .binding import (EXPORTS, LIB_PATH, SR_DIRECT, SR_DL, SR_FP64, SR_MIXED, SR_SL, SR_TREE, SrError, SrParams,
+                      load_library, sr_create, sr_default_params, sr_destroy, sr_eval, sr_set_density,
+                      sr_set_params, sr_set_surface, sr_version, sr_set_profiling, sr_get_profile,
+                      SR_PHASE_FAR, SR_PHASE_NEAR)
+from .evaluator import Evaluator
+
+__all__ = ["EXPORTS", "LIB_PATH", "SR_DIRECT", "SR_DL", "SR_FP64", "SR_MIXED", "SR_SL", "SR_TREE", "SrError",
+           "SrParams", "load_library", "sr_create", "sr_default_params", "sr_destroy", "sr_eval", "sr_set_density",
+           "sr_set_params", "sr_set_surface", "sr_version", "Evaluator", "sr_set_profiling", "sr_get_profile",
+           "SR_PHASE_FAR", "SR_PHASE_NEAR"]

@@ -1,0 +1,163 @@
+"""Thin ctypes binding of libstokesreg.so (C ABI in include/stokesreg.h).
+
+Argument marshalling only: torch supplies device memory and the stream; every step of the method
+runs in the library's HIP kernels.  There is no CPU fallback: if the library is not built, or no GPU
+is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstokesreg.so")
+
+SR_OK, SR_EINVAL, SR_ENOMEM, SR_ENODEV, SR_ESTATE, SR_EHIP, SR_ENOCONV = 0, -1, -2, -3, -4, -5, -6
+SR_SL, SR_DL = 1, 2
+SR_FP64, SR_MIXED = 0, 1
+SR_DIRECT, SR_TREE = 0, 1
+_NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR_ESTATE", -5: "SR_EHIP",
+          -6: "SR_ENOCONV"}
+
+# every symbol the header declares; the CPU test-suite checks that the library exports each one
+EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
+           "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_last_error", "sr_version")
+SR_PHASE_FAR, SR_PHASE_NEAR, SR_NPHASES = 0, 1, 2
+
+
+class SrParams(C.Structure):
+    _fields_ = [("h", C.c_double), ("rho", C.c_double * 3), ("cutoff", C.c_double), ("precision", C.c_int),
+                ("far_method", C.c_int), ("tree_degree", C.c_int), ("tree_theta", C.c_double),
+                ("tree_leaf", C.c_int)]
+
+
+class SrError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libstokesreg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950) first")
+    L = C.CDLL(path)
+    vp, d, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+    L.sr_default_params.argtypes = [C.POINTER(SrParams)]
+    L.sr_default_params.restype = None
+    L.sr_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.sr_destroy.argtypes = [vp]
+    L.sr_set_params.argtypes = [vp, C.POINTER(SrParams)]
+    L.sr_set_surface.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.sr_set_density.argtypes = [vp, C.c_int, vp, vp]
+    L.sr_eval.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.sr_set_profiling.argtypes = [vp, C.c_int]
+    L.sr_get_profile.argtypes = [vp, d, C.POINTER(C.c_int64)]
+    L.sr_last_error.argtypes = []
+    L.sr_last_error.restype = C.c_char_p
+    L.sr_version.argtypes = []
+    L.sr_version.restype = C.c_char_p
+    for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
+               "sr_set_profiling", "sr_get_profile"):
+        getattr(L, fn).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(fn: str, st: int) -> None:
+    if st != SR_OK:
+        raise SrError(fn, st, load_library().sr_last_error().decode())
+
+
+def _ptr(t, name: str, shape_last=None):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA torch.Tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous float64 tensor")
+    if shape_last is not None and (t.dim() != 2 or t.shape[1] != shape_last):
+        raise ValueError(f"{name}: expected shape (k, {shape_last}), got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def sr_default_params() -> SrParams:
+    p = SrParams()
+    load_library().sr_default_params(C.byref(p))
+    return p
+
+
+def sr_create(device: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    _check("sr_create", load_library().sr_create(C.byref(h), int(device)))
+    return h
+
+
+def sr_destroy(ctx) -> None:
+    _check("sr_destroy", load_library().sr_destroy(ctx))
+
+
+def sr_set_params(ctx, params: SrParams) -> None:
+    _check("sr_set_params", load_library().sr_set_params(ctx, C.byref(params)))
+
+
+def sr_set_surface(ctx, x, nrm, w, stream=None) -> None:
+    n = int(x.shape[0])
+    if w.dim() != 1 or w.shape[0] != n or nrm.shape[0] != n:
+        raise ValueError("sr_set_surface: x, nrm, w sizes differ")
+    _check("sr_set_surface", load_library().sr_set_surface(ctx, n, _ptr(x, "x", 3), _ptr(nrm, "nrm", 3),
+                                                           _ptr(w, "w"), _stream(stream)))
+
+
+def sr_set_density(ctx, layer: int, dens, stream=None) -> None:
+    _check("sr_set_density", load_library().sr_set_density(ctx, int(layer), _ptr(dens, "dens", 3), _stream(stream)))
+
+
+def sr_eval(ctx, layers: int, y, x0, n0, b, f0=None, q0=None, u=None, v=None, u_delta=None, v_delta=None,
+            stream=None) -> None:
+    m = int(y.shape[0])
+    for name, t, last in (("x0", x0, 3), ("n0", n0, 3), ("f0", f0, 3), ("q0", q0, 3), ("u", u, 3), ("v", v, 3)):
+        if t is not None and (t.dim() != 2 or t.shape[0] != m or t.shape[1] != last):
+            raise ValueError(f"sr_eval: {name} must have shape ({m}, 3)")
+    if b.dim() != 1 or b.shape[0] != m:
+        raise ValueError(f"sr_eval: b must have shape ({m},)")
+    for name, t in (("u_delta", u_delta), ("v_delta", v_delta)):
+        if t is not None and tuple(t.shape) != (m, 3, 3):
+            raise ValueError(f"sr_eval: {name} must have shape ({m}, 3, 3)")
+    _check("sr_eval", load_library().sr_eval(ctx, int(layers), m, _ptr(y, "y", 3), _ptr(x0, "x0", 3),
+                                             _ptr(n0, "n0", 3), _ptr(b, "b"), _ptr(f0, "f0"), _ptr(q0, "q0"),
+                                             _ptr(u, "u"), _ptr(v, "v"), _ptr(u_delta, "u_delta"),
+                                             _ptr(v_delta, "v_delta"), _stream(stream)))
+
+
+def sr_set_profiling(ctx, on: bool) -> None:
+    _check("sr_set_profiling", load_library().sr_set_profiling(ctx, int(bool(on))))
+
+
+def sr_get_profile(ctx):
+    """Returns ([ms_far, ms_near], number_of_evaluations) accumulated since the last call."""
+    ms = (C.c_double * SR_NPHASES)()
+    ne = C.c_int64()
+    _check("sr_get_profile", load_library().sr_get_profile(ctx, ms, C.byref(ne)))
+    return list(ms), int(ne.value)
+
+
+def sr_version() -> str:
+    return load_library().sr_version().decode()

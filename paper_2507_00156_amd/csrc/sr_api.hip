@@ -1,0 +1,455 @@
+// C-ABI entry points of libstokesreg (declared and documented in include/stokesreg.h).
+//
+// Host responsibilities: argument validation, ownership of device buffers, the spatial index of the
+// sources (a uniform cell grid whose side is at least the near radius cutoff * max_j delta_j, built
+// by a counting sort on the host when the surface or the radius changes), and kernel launches on the
+// caller's stream.  All arithmetic of the method runs in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sr_internal.h"
+
+using namespace sr;
+
+namespace {
+
+thread_local std::string g_err;
+
+sr_status fail(sr_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define SR_HIP(call)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(e_ == hipErrorOutOfMemory ? SR_ENOMEM : SR_EHIP, "%s failed: %s", #call,     \
+                        hipGetErrorString(e_));                                                      \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;  // elements
+    hipError_t reserve(size_t n)
+    {
+        if (n <= cap && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
+        if (e == hipSuccess) cap = n;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+bool is_pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+struct sr_ctx {
+    int device = 0;
+    sr_params prm{};
+    bool have_params = false;
+
+    int64_t n = 0;
+    bool have_surface = false, have_sl = false, have_dl = false;
+    std::vector<double> hx;  // host copy of the points (caller order), for the spatial index
+
+    DevBuf<double> x, nrm, w, f, q;  // caller order
+    DevBuf<int64_t> perm;            // sorted record i <- caller index perm[i]
+    DevBuf<int> cell_start;
+    DevBuf<SrcRec<double>> rec64;
+    DevBuf<SrcRec<float>> rec32;
+    DevBuf<double> part;  // far-field partial sums
+
+    CellGrid grid{};
+    double grid_rnear = -1.0;
+    bool layout_dirty = true, pack_dirty = true;
+
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;     // created events, reused
+    std::vector<hipEvent_t> ev_recorded; // 3 per profiled evaluation: start, far done, near done
+
+    ~sr_ctx()
+    {
+        x.release();
+        nrm.release();
+        w.release();
+        f.release();
+        q.release();
+        perm.release();
+        cell_start.release();
+        rec64.release();
+        rec32.release();
+        part.release();
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_recorded) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+double near_radius(const sr_params &p)
+{
+    return p.cutoff * std::max(p.rho[0], std::max(p.rho[1], p.rho[2])) * p.h;
+}
+
+// Uniform grid of cells of side >= the near radius (plus a relative margin of 1e-5, so that a pair
+// classified near by the single-precision test always lies in neighbouring cells), sources sorted
+// by cell with a stable counting sort.
+sr_status build_layout(sr_ctx *c, hipStream_t s)
+{
+    const double rnear = near_radius(c->prm);
+    const int64_t n = c->n;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], c->hx[3 * i + d]);
+            hi[d] = std::max(hi[d], c->hx[3 * i + d]);
+        }
+    double side = rnear * (1.0 + 1e-5);
+    const int64_t kMaxCells = int64_t(1) << 22;
+    int g[3];
+    for (;;) {
+        int64_t tot = 1;
+        for (int d = 0; d < 3; ++d) {
+            g[d] = (int)std::max<double>(1.0, std::floor((hi[d] - lo[d]) / side) + 1.0);
+            tot *= g[d];
+        }
+        if (tot <= kMaxCells) break;
+        side *= 1.25;
+    }
+    const double inv_side = 1.0 / side;
+    const int64_t ncell = (int64_t)g[0] * g[1] * g[2];
+    std::vector<int> key(n);
+    std::vector<int> start(ncell + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        int ic[3];
+        for (int d = 0; d < 3; ++d) {
+            double u = std::floor((c->hx[3 * i + d] - lo[d]) * inv_side);
+            ic[d] = (int)std::min<double>(std::max(u, 0.0), g[d] - 1);
+        }
+        key[i] = (ic[0] * g[1] + ic[1]) * g[2] + ic[2];
+        start[key[i] + 1]++;
+    }
+    for (int64_t k = 0; k < ncell; ++k) start[k + 1] += start[k];
+    std::vector<int64_t> perm(n);
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int64_t i = 0; i < n; ++i) perm[fill[key[i]]++] = i;
+    }
+    SR_HIP(c->perm.reserve(n));
+    SR_HIP(c->cell_start.reserve(ncell + 1));
+    SR_HIP(hipMemcpyAsync(c->perm.p, perm.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SR_HIP(hipMemcpyAsync(c->cell_start.p, start.data(), (ncell + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    // the host vectors die at return: wait for the copies
+    SR_HIP(hipStreamSynchronize(s));
+    for (int d = 0; d < 3; ++d) {
+        c->grid.lo[d] = lo[d];
+        c->grid.g[d] = g[d];
+    }
+    c->grid.inv_side = inv_side;
+    c->grid_rnear = rnear;
+    c->layout_dirty = false;
+    c->pack_dirty = true;
+    return SR_OK;
+}
+
+sr_status ensure_packed(sr_ctx *c, hipStream_t s)
+{
+    if (c->layout_dirty || c->grid_rnear != near_radius(c->prm)) {
+        sr_status st = build_layout(c, s);
+        if (st != SR_OK) return st;
+    }
+    if (c->pack_dirty) {
+        SR_HIP(c->rec64.reserve(c->n));
+        SR_HIP(c->rec32.reserve(c->n));
+        SR_HIP(launch_pack(c->x.p, c->nrm.p, c->w.p, c->have_sl ? c->f.p : nullptr, c->have_dl ? c->q.p : nullptr,
+                           c->perm.p, c->n, c->rec64.p, c->rec32.p, s));
+        c->pack_dirty = false;
+    }
+    return SR_OK;
+}
+
+sr_status record_event(sr_ctx *c, hipStream_t s)
+{
+    hipEvent_t e;
+    if (!c->ev_pool.empty()) {
+        e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+    } else {
+        SR_HIP(hipEventCreate(&e));
+    }
+    c->ev_recorded.push_back(e);
+    SR_HIP(hipEventRecord(e, s));
+    return SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sr_default_params(sr_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->h = 0.0;
+    p->rho[0] = 2.0;
+    p->rho[1] = 3.0;
+    p->rho[2] = 4.0;
+    p->cutoff = 6.0;
+    p->precision = SR_FP64;
+    p->far_method = SR_DIRECT;
+    p->tree_degree = 8;
+    p->tree_theta = 0.7;
+    p->tree_leaf = 2000;
+}
+
+const char *sr_last_error(void) { return g_err.c_str(); }
+
+const char *sr_version(void) { return "stokesreg 0.1 (gfx950)"; }
+
+sr_status sr_create(sr_ctx **out, int device)
+{
+    g_err.clear();
+    if (!out) return fail(SR_EINVAL, "sr_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(SR_ENODEV, "sr_create: no HIP device available");
+    if (device < 0 || device >= count)
+        return fail(SR_ENODEV, "sr_create: device %d does not exist (%d devices)", device, count);
+    sr_ctx *c = new (std::nothrow) sr_ctx();
+    if (!c) return fail(SR_ENOMEM, "sr_create: out of host memory");
+    c->device = device;
+    sr_default_params(&c->prm);
+    *out = c;
+    return SR_OK;
+}
+
+sr_status sr_destroy(sr_ctx *c)
+{
+    g_err.clear();
+    if (!c) return SR_OK;
+    {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        delete c;
+    }
+    return SR_OK;
+}
+
+sr_status sr_set_params(sr_ctx *c, const sr_params *p)
+{
+    g_err.clear();
+    if (!c || !p) return fail(SR_EINVAL, "sr_set_params: NULL argument");
+    if (!is_pos_finite(p->h)) return fail(SR_EINVAL, "sr_set_params: h must be positive and finite");
+    for (int j = 0; j < 3; ++j)
+        if (!is_pos_finite(p->rho[j])) return fail(SR_EINVAL, "sr_set_params: rho[%d] must be positive", j);
+    if (p->rho[0] == p->rho[1] || p->rho[0] == p->rho[2] || p->rho[1] == p->rho[2])
+        return fail(SR_EINVAL, "sr_set_params: the three rho must be distinct");
+    if (!is_pos_finite(p->cutoff)) return fail(SR_EINVAL, "sr_set_params: cutoff must be positive");
+    if (p->precision != SR_FP64 && p->precision != SR_MIXED)
+        return fail(SR_EINVAL, "sr_set_params: precision must be SR_FP64 or SR_MIXED");
+    if (p->far_method != SR_DIRECT && p->far_method != SR_TREE)
+        return fail(SR_EINVAL, "sr_set_params: far_method must be SR_DIRECT or SR_TREE");
+    if (p->far_method == SR_TREE) {
+        if (p->tree_degree < 1 || p->tree_degree > 16)
+            return fail(SR_EINVAL, "sr_set_params: tree_degree must be in 1..16");
+        if (!(p->tree_theta >= 0.0 && p->tree_theta < 1.0))
+            return fail(SR_EINVAL, "sr_set_params: tree_theta must be in [0, 1)");
+        if (p->tree_leaf < 1) return fail(SR_EINVAL, "sr_set_params: tree_leaf must be >= 1");
+        return fail(SR_EINVAL, "sr_set_params: SR_TREE is not available in this build");
+    }
+    c->prm = *p;
+    c->have_params = true;
+    return SR_OK;
+}
+
+sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nrm, const double *w, void *stream)
+{
+    g_err.clear();
+    if (!c) return fail(SR_EINVAL, "sr_set_surface: ctx is NULL");
+    if (n < 1 || n > (int64_t(1) << 30)) return fail(SR_EINVAL, "sr_set_surface: n = %lld out of range", (long long)n);
+    if (!x || !nrm || !w) return fail(SR_EINVAL, "sr_set_surface: NULL array");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(SR_ENODEV, "sr_set_surface: cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> hx(3 * n), hn(3 * n), hw(n);
+    SR_HIP(hipMemcpyAsync(hx.data(), x, 3 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    SR_HIP(hipMemcpyAsync(hn.data(), nrm, 3 * n * sizeof(double), hipMemcpyDeviceToHost, s));
+    SR_HIP(hipMemcpyAsync(hw.data(), w, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    SR_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(hw[i]) || hw[i] < 0.0)
+            return fail(SR_EINVAL, "sr_set_surface: weight %lld is negative or not finite", (long long)i);
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(hx[3 * i + d]) || !std::isfinite(hn[3 * i + d]))
+                return fail(SR_EINVAL, "sr_set_surface: point or normal %lld not finite", (long long)i);
+    }
+    SR_HIP(c->x.reserve(3 * n));
+    SR_HIP(c->nrm.reserve(3 * n));
+    SR_HIP(c->w.reserve(n));
+    SR_HIP(hipMemcpyAsync(c->x.p, x, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    SR_HIP(hipMemcpyAsync(c->nrm.p, nrm, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    SR_HIP(hipMemcpyAsync(c->w.p, w, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    c->n = n;
+    c->hx.swap(hx);
+    c->have_surface = true;
+    c->have_sl = c->have_dl = false;
+    c->layout_dirty = true;
+    c->pack_dirty = true;
+    return SR_OK;
+}
+
+sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
+{
+    g_err.clear();
+    if (!c || !dens) return fail(SR_EINVAL, "sr_set_density: NULL argument");
+    if (layer != SR_SL && layer != SR_DL) return fail(SR_EINVAL, "sr_set_density: layer must be SR_SL or SR_DL");
+    if (!c->have_surface) return fail(SR_ESTATE, "sr_set_density: set the surface first");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(SR_ENODEV, "sr_set_density: cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<double> &dst = layer == SR_SL ? c->f : c->q;
+    SR_HIP(dst.reserve(3 * c->n));
+    SR_HIP(hipMemcpyAsync(dst.p, dens, 3 * c->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (layer == SR_SL)
+        c->have_sl = true;
+    else
+        c->have_dl = true;
+    c->pack_dirty = true;
+    return SR_OK;
+}
+
+sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const double *x0, const double *n0,
+                  const double *b, const double *f0, const double *q0, double *u, double *v, double *u_delta,
+                  double *v_delta, void *stream)
+{
+    g_err.clear();
+    if (!c) return fail(SR_EINVAL, "sr_eval: ctx is NULL");
+    if (layers != SR_SL && layers != SR_DL && layers != (SR_SL | SR_DL))
+        return fail(SR_EINVAL, "sr_eval: layers must be SR_SL, SR_DL or both");
+    if (m < 0 || m > (int64_t(1) << 30)) return fail(SR_EINVAL, "sr_eval: m = %lld out of range", (long long)m);
+    if (!c->have_params) return fail(SR_ESTATE, "sr_eval: parameters not set");
+    if (!c->have_surface) return fail(SR_ESTATE, "sr_eval: surface not set");
+    if ((layers & SR_SL) && !c->have_sl) return fail(SR_ESTATE, "sr_eval: single-layer density not set");
+    if ((layers & SR_DL) && !c->have_dl) return fail(SR_ESTATE, "sr_eval: double-layer density not set");
+    if (m == 0) return SR_OK;
+    if (!y || !x0 || !n0 || !b) return fail(SR_EINVAL, "sr_eval: NULL target array");
+    if ((layers & SR_SL) && (!f0 || !u)) return fail(SR_EINVAL, "sr_eval: SR_SL needs f0 and u");
+    if ((layers & SR_DL) && (!q0 || !v)) return fail(SR_EINVAL, "sr_eval: SR_DL needs q0 and v");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(SR_ENODEV, "sr_eval: cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+
+    sr_status st = ensure_packed(c, s);
+    if (st != SR_OK) return st;
+
+    EvalArgs a{};
+    a.layers = layers;
+    a.m = m;
+    a.y = y;
+    a.x0 = x0;
+    a.n0 = n0;
+    a.b = b;
+    a.f0 = f0;
+    a.q0 = q0;
+    a.u = u;
+    a.v = v;
+    a.u_delta = u_delta;
+    a.v_delta = v_delta;
+
+    DevParams dp{};
+    dp.h = c->prm.h;
+    for (int j = 0; j < 3; ++j) {
+        dp.rho[j] = c->prm.rho[j];
+        dp.inv_delta[j] = 1.0 / (c->prm.rho[j] * c->prm.h);
+    }
+    dp.cutoff = c->prm.cutoff;
+    dp.rnear = c->grid_rnear;
+    dp.precision = c->prm.precision;
+
+    SR_HIP(c->part.reserve((size_t)kFarSplits * 6 * (size_t)m));
+    if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
+    SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, c->part.p, s));
+    if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
+    SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->cell_start.p, c->grid, a, dp,
+                                c->part.p, kFarSplits, s));
+    if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
+    return SR_OK;
+}
+
+sr_status sr_set_profiling(sr_ctx *c, int on)
+{
+    g_err.clear();
+    if (!c) return fail(SR_EINVAL, "sr_set_profiling: ctx is NULL");
+    c->profiling = on != 0;
+    return SR_OK;
+}
+
+sr_status sr_get_profile(sr_ctx *c, double *ms, int64_t *evals)
+{
+    g_err.clear();
+    if (!c || !ms || !evals) return fail(SR_EINVAL, "sr_get_profile: NULL argument");
+    DeviceGuard g(c->device);
+    for (int k = 0; k < SR_NPHASES; ++k) ms[k] = 0.0;
+    const size_t ne = c->ev_recorded.size() / 3;
+    for (size_t i = 0; i < ne; ++i) {
+        hipEvent_t *e = &c->ev_recorded[3 * i];
+        SR_HIP(hipEventSynchronize(e[2]));
+        float a = 0.f, b = 0.f;
+        SR_HIP(hipEventElapsedTime(&a, e[0], e[1]));
+        SR_HIP(hipEventElapsedTime(&b, e[1], e[2]));
+        ms[SR_PHASE_FAR] += a;
+        ms[SR_PHASE_NEAR] += b;
+    }
+    *evals = (int64_t)ne;
+    for (hipEvent_t e : c->ev_recorded) c->ev_pool.push_back(e);
+    c->ev_recorded.clear();
+    return SR_OK;
+}
+
+}  // extern "C"

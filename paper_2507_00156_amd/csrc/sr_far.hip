@@ -1,0 +1,151 @@
+// Far-field direct sum of the extrapolated-regularization method (paper section 3.3, eq. (near_far)):
+// for every target, the pairs farther than the near radius are summed ONCE with the original
+// Stokeslet (eq. (Stokeslet)) and stresslet (eq. (Stresslet)) kernels, applied to the subtracted
+// densities of eqs. (Stokes_SL1), (Stokes_DL1).  The result is shared by the three smoothing lengths.
+//
+// Work decomposition (MI355X, 256 CUs in 8 XCDs):
+//   - one lane owns TPL targets; each workgroup (256 lanes) owns 256*TPL targets and one of
+//     kFarSplits contiguous source ranges; blockIdx.x % 8 selects the range, so the round-robin
+//     dispatch over XCDs gives every XCD's L2 a single eighth of the source records;
+//   - the source index is wavefront-uniform, so each record is fetched once per wavefront through
+//     the scalar data cache and feeds the VALU as scalar operands: no LDS traffic, no barriers;
+//   - near pairs (r^2 <= rc2 by the shared pair_r2 test) are selected out (not multiplied by zero:
+//     r can be 0);
+//   - mixed precision: pair kernels in FP32, 64-pair FP32 partial sums promoted to FP64;
+//   - output: per-split partial sums part[split][channel][target], channel 0..2 = single-layer
+//     sum of S g, channel 3..5 = sum of d (d.a)(d.m) / r^5 (the -6 and 1/(8 pi) are applied
+//     when the near-field kernel combines the parts).
+#include "sr_internal.h"
+
+namespace sr {
+namespace {
+
+constexpr int kTile = 64;  // FP32 partial-sum length before promotion to FP64
+
+__device__ __forceinline__ float rsqrt_t(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double rsqrt_t(double v) { return rsqrt(v); }
+
+template <typename T, bool SL, bool DL, int TPL>
+__global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__restrict__ src, int n, int chunk,
+                                                            const double *__restrict__ y,
+                                                            const double *__restrict__ n0,
+                                                            const double *__restrict__ f0,
+                                                            const double *__restrict__ q0, int m, T rc2,
+                                                            double *__restrict__ part)
+{
+    const int split = blockIdx.x % kFarSplits;
+    const int tile = blockIdx.x / kFarSplits;
+    const int p0 = split * chunk;
+    const int p1 = min(n, p0 + chunk);
+
+    T ty[TPL][3], tc[TPL], tq[TPL][3];
+    int tix[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        const int t = (tile * TPL + k) * kBlock + (int)threadIdx.x;
+        tix[k] = t;
+        const int tt = t < m ? t : m - 1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ty[k][i] = (T)y[3 * tt + i];
+        tc[k] = 0;
+        if (SL) tc[k] = (T)(f0[3 * tt] * n0[3 * tt] + f0[3 * tt + 1] * n0[3 * tt + 1] + f0[3 * tt + 2] * n0[3 * tt + 2]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) tq[k][i] = DL ? (T)q0[3 * tt + i] : (T)0;
+    }
+
+    double acc[TPL][6];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[k][c] = 0.0;
+
+    for (int pb = p0; pb < p1; pb += kTile) {
+        const int pe = min(pb + kTile, p1);
+        T a[TPL][6];
+#pragma unroll
+        for (int k = 0; k < TPL; ++k)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) a[k][c] = 0;
+#pragma unroll 2
+        for (int p = pb; p < pe; ++p) {
+            const SrcRec<T> s = src[p];
+#pragma unroll
+            for (int k = 0; k < TPL; ++k) {
+                const T dx = ty[k][0] - s.x, dy = ty[k][1] - s.y, dz = ty[k][2] - s.z;
+                const T r2 = pair_r2(ty[k][0], ty[k][1], ty[k][2], s.x, s.y, s.z);
+                const T ir = r2 > rc2 ? rsqrt_t(r2) : (T)0;
+                const T ir2 = ir * ir;
+                const T ir3 = ir2 * ir;
+                if (SL) {
+                    const T gx = s.fw[0] - tc[k] * s.nw[0];
+                    const T gy = s.fw[1] - tc[k] * s.nw[1];
+                    const T gz = s.fw[2] - tc[k] * s.nw[2];
+                    const T sc = (dx * gx + dy * gy + dz * gz) * ir3;
+                    a[k][0] += gx * ir + dx * sc;
+                    a[k][1] += gy * ir + dy * sc;
+                    a[k][2] += gz * ir + dz * sc;
+                }
+                if (DL) {
+                    const T ax = s.q[0] - tq[k][0], ay = s.q[1] - tq[k][1], az = s.q[2] - tq[k][2];
+                    const T da = dx * ax + dy * ay + dz * az;
+                    const T dm = dx * s.nw[0] + dy * s.nw[1] + dz * s.nw[2];
+                    const T co = da * dm * (ir3 * ir2);
+                    a[k][3] += dx * co;
+                    a[k][4] += dy * co;
+                    a[k][5] += dz * co;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TPL; ++k)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[k][c] += (double)a[k][c];
+    }
+
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+        if (tix[k] < m) {
+            const size_t base = (size_t)split * 6 * (size_t)m + (size_t)tix[k];
+            if (SL)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) part[base + (size_t)c * m] = acc[k][c];
+            if (DL)
+#pragma unroll
+                for (int c = 3; c < 6; ++c) part[base + (size_t)c * m] = acc[k][c];
+        }
+    }
+}
+
+template <typename T, bool SL, bool DL>
+hipError_t launch_t(const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, double *part, hipStream_t s)
+{
+    constexpr int TPL = 2;
+    const int m = (int)a.m;
+    const int tiles = (m + kBlock * TPL - 1) / (kBlock * TPL);
+    const int chunk = (int)((n + kFarSplits - 1) / kFarSplits);
+    dim3 grid(tiles * kFarSplits), block(kBlock);
+    hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0, a.f0,
+                       a.q0, m, rc2, part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch(int layers, const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, double *part,
+                    hipStream_t s)
+{
+    if (layers == (SR_SL | SR_DL)) return launch_t<T, true, true>(rec, n, a, rc2, part, s);
+    if (layers == SR_SL) return launch_t<T, true, false>(rec, n, a, rc2, part, s);
+    return launch_t<T, false, true>(rec, n, a, rc2, part, s);
+}
+
+}  // namespace
+
+hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
+                             int64_t n, const EvalArgs &a, double rnear, double *part, hipStream_t s)
+{
+    const double rc2 = rnear * rnear;
+    if (precision == SR_MIXED) return dispatch<float>(layers, rec32, n, a, (float)rc2, part, s);
+    return dispatch<double>(layers, rec64, n, a, rc2, part, s);
+}
+
+}  // namespace sr

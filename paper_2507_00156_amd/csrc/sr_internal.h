@@ -1,0 +1,89 @@
+// Internal declarations of libstokesreg: device data layout, the shared pair classification, and
+// the kernel launchers.  HIP for gfx950 (wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "stokesreg.h"
+
+namespace sr {
+
+// Source splits of the direct far field.  Workgroups are dispatched round-robin over the 8 XCDs,
+// so split = blockIdx.x % 8 keeps each XCD's L2 on one eighth of the sources.
+constexpr int kFarSplits = 8;
+constexpr int kBlock = 256;       // threads per workgroup (4 waves of 64)
+constexpr int kWave = 64;
+
+// One quadrature point with its density channels, array-of-records so that a wavefront-uniform
+// index loads a whole record through the scalar cache:
+//   x      point
+//   fw     f(x) w        (single layer; zero until an SL density is set)
+//   nw     n(x) w        (both layers: the subtraction term of eq. (Stokes_SL1) and the n_k w of
+//                         eq. (Stokes_DL1))
+//   q      q(x)          (double layer; zero until a DL density is set)
+template <typename T>
+struct alignas(16) SrcRec {
+    T x, y, z;
+    T fw[3];
+    T nw[3];
+    T q[3];
+};
+static_assert(sizeof(SrcRec<float>) == 48, "record layout");
+static_assert(sizeof(SrcRec<double>) == 96, "record layout");
+
+// Squared distance used to classify a pair as near (r^2 <= rc2) or far.  The far-field and the
+// near-field kernels call this same function on the same rounded operands, so every pair is
+// assigned to exactly one of the two sums.  Explicit fma keeps the instruction sequence fixed.
+__device__ __forceinline__ float pair_r2(float yx, float yy, float yz, float xx, float xy, float xz)
+{
+    const float dx = yx - xx, dy = yy - xy, dz = yz - xz;
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+__device__ __forceinline__ double pair_r2(double yx, double yy, double yz, double xx, double xy, double xz)
+{
+    const double dx = yx - xx, dy = yy - xy, dz = yz - xz;
+    return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+}
+
+// Uniform cell grid over the sources (side >= near radius): cells in x-major, z-fastest order;
+// sources are stored sorted by cell, cell c owning records [cell_start[c], cell_start[c+1]).
+struct CellGrid {
+    double lo[3];
+    double inv_side;
+    int g[3];
+};
+
+struct EvalArgs {
+    int layers;          // SR_SL | SR_DL bits
+    int64_t m;
+    const double *y, *x0, *n0, *b, *f0, *q0;
+    double *u, *v, *u_delta, *v_delta;
+};
+
+struct DevParams {
+    double h;
+    double rho[3];
+    double inv_delta[3];
+    double cutoff;       // in t = r / delta
+    double rnear;        // cutoff * max_j delta_j
+    int precision;
+};
+
+// ---- kernel launchers (return hipSuccess or the launch error) ----
+hipError_t launch_pack(const double *x, const double *nrm, const double *w, const double *f, const double *q,
+                       const int64_t *perm, int64_t n, SrcRec<double> *rec64, SrcRec<float> *rec32,
+                       hipStream_t s);
+
+hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
+                             int64_t n, const EvalArgs &a, double rnear, double *part, hipStream_t s);
+
+hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
+                                const SrcRec<float> *rec32, const int *cell_start, const CellGrid &grid,
+                                const EvalArgs &a, const DevParams &p, const double *part, int nparts,
+                                hipStream_t s);
+
+}  // namespace sr
