@@ -42,7 +42,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle baseline")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a device-to-device copy of 256 MiB (calibrates the FETCH_SIZE / WRITE_SIZE "
+                         "counters against known bytes) and exit")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+
+    n = 256 * 1024 * 1024 // 8
+    a = torch.arange(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
 
 
 def time_eval(P, ev, args_dev, steps, warmup, profile):
@@ -101,6 +117,9 @@ def cpu_baseline(cfg, target_seconds):
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               "(the multi-GPU sharding is described in the design notes, not implemented)", file=sys.stderr)

@@ -98,6 +98,8 @@ struct sr_ctx {
     DevBuf<int> cell_start;
     DevBuf<SrcRec<double>> rec64;
     DevBuf<SrcRec<float>> rec32;
+    DevBuf<Pos4<double>> pos64;
+    DevBuf<Pos4<float>> pos32;
     DevBuf<double> part;  // far-field partial sums
 
     CellGrid grid{};
@@ -119,6 +121,8 @@ struct sr_ctx {
         cell_start.release();
         rec64.release();
         rec32.release();
+        pos64.release();
+        pos32.release();
         part.release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev_recorded) (void)hipEventDestroy(e);
@@ -206,8 +210,10 @@ sr_status ensure_packed(sr_ctx *c, hipStream_t s)
     if (c->pack_dirty) {
         SR_HIP(c->rec64.reserve(c->n));
         SR_HIP(c->rec32.reserve(c->n));
+        SR_HIP(c->pos64.reserve(c->n));
+        SR_HIP(c->pos32.reserve(c->n));
         SR_HIP(launch_pack(c->x.p, c->nrm.p, c->w.p, c->have_sl ? c->f.p : nullptr, c->have_dl ? c->q.p : nullptr,
-                           c->perm.p, c->n, c->rec64.p, c->rec32.p, s));
+                           c->perm.p, c->n, c->rec64.p, c->rec32.p, c->pos64.p, c->pos32.p, s));
         c->pack_dirty = false;
     }
     return SR_OK;
@@ -404,9 +410,12 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
 
     DevParams dp{};
     dp.h = c->prm.h;
-    for (int j = 0; j < 3; ++j) {
-        dp.rho[j] = c->prm.rho[j];
-        dp.inv_delta[j] = 1.0 / (c->prm.rho[j] * c->prm.h);
+    int ord[3] = {0, 1, 2};
+    std::sort(ord, ord + 3, [&](int i, int j) { return c->prm.rho[i] < c->prm.rho[j]; });
+    for (int o = 0; o < 3; ++o) {
+        dp.ord[o] = ord[o];
+        dp.rho[o] = c->prm.rho[ord[o]];
+        dp.inv_delta[o] = 1.0 / (dp.rho[o] * c->prm.h);
     }
     dp.cutoff = c->prm.cutoff;
     dp.rnear = c->grid_rnear;
@@ -416,8 +425,8 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, c->part.p, s));
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
-    SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->cell_start.p, c->grid, a, dp,
-                                c->part.p, kFarSplits, s));
+    SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p, c->cell_start.p,
+                                c->grid, a, dp, c->part.p, kFarSplits, s));
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     return SR_OK;
 }

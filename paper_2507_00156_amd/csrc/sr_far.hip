@@ -24,6 +24,8 @@ constexpr int kTile = 64;  // FP32 partial-sum length before promotion to FP64
 
 __device__ __forceinline__ float rsqrt_t(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_t(double v) { return rsqrt(v); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename T, bool SL, bool DL, int TPL>
 __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__restrict__ src, int n, int chunk,
@@ -81,18 +83,19 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
                     const T gy = s.fw[1] - tc[k] * s.nw[1];
                     const T gz = s.fw[2] - tc[k] * s.nw[2];
                     const T sc = (dx * gx + dy * gy + dz * gz) * ir3;
-                    a[k][0] += gx * ir + dx * sc;
-                    a[k][1] += gy * ir + dy * sc;
-                    a[k][2] += gz * ir + dz * sc;
+                    // explicit chains: a += g/r + d s as two fused multiply-adds per component
+                    a[k][0] = fma_t(dx, sc, fma_t(gx, ir, a[k][0]));
+                    a[k][1] = fma_t(dy, sc, fma_t(gy, ir, a[k][1]));
+                    a[k][2] = fma_t(dz, sc, fma_t(gz, ir, a[k][2]));
                 }
                 if (DL) {
                     const T ax = s.q[0] - tq[k][0], ay = s.q[1] - tq[k][1], az = s.q[2] - tq[k][2];
                     const T da = dx * ax + dy * ay + dz * az;
                     const T dm = dx * s.nw[0] + dy * s.nw[1] + dz * s.nw[2];
                     const T co = da * dm * (ir3 * ir2);
-                    a[k][3] += dx * co;
-                    a[k][4] += dy * co;
-                    a[k][5] += dz * co;
+                    a[k][3] = fma_t(dx, co, a[k][3]);
+                    a[k][4] = fma_t(dy, co, a[k][4]);
+                    a[k][5] = fma_t(dz, co, a[k][5]);
                 }
             }
         }

@@ -35,6 +35,13 @@ struct alignas(16) SrcRec {
 static_assert(sizeof(SrcRec<float>) == 48, "record layout");
 static_assert(sizeof(SrcRec<double>) == 96, "record layout");
 
+// Candidate positions for the near-pair test, 16/32-byte aligned so a lane fetches one in one or two
+// vector loads (w unused).
+template <typename T>
+struct alignas(4 * sizeof(T)) Pos4 {
+    T x, y, z, w;
+};
+
 // Squared distance used to classify a pair as near (r^2 <= rc2) or far.  The far-field and the
 // near-field kernels call this same function on the same rounded operands, so every pair is
 // assigned to exactly one of the two sums.  Explicit fma keeps the instruction sequence fixed.
@@ -64,10 +71,13 @@ struct EvalArgs {
     double *u, *v, *u_delta, *v_delta;
 };
 
+// The three smoothing lengths in ascending order (the extrapolation is symmetric under reordering
+// them): rho[o], inv_delta[o] for sorted position o; ord[o] is the caller's index of that delta.
 struct DevParams {
     double h;
     double rho[3];
     double inv_delta[3];
+    int ord[3];
     double cutoff;       // in t = r / delta
     double rnear;        // cutoff * max_j delta_j
     int precision;
@@ -76,14 +86,14 @@ struct DevParams {
 // ---- kernel launchers (return hipSuccess or the launch error) ----
 hipError_t launch_pack(const double *x, const double *nrm, const double *w, const double *f, const double *q,
                        const int64_t *perm, int64_t n, SrcRec<double> *rec64, SrcRec<float> *rec32,
-                       hipStream_t s);
+                       Pos4<double> *pos64, Pos4<float> *pos32, hipStream_t s);
 
 hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
                              int64_t n, const EvalArgs &a, double rnear, double *part, hipStream_t s);
 
 hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
-                                const SrcRec<float> *rec32, const int *cell_start, const CellGrid &grid,
-                                const EvalArgs &a, const DevParams &p, const double *part, int nparts,
-                                hipStream_t s);
+                                const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,
+                                const CellGrid &grid, const EvalArgs &a, const DevParams &p, const double *part,
+                                int nparts, hipStream_t s);
 
 }  // namespace sr

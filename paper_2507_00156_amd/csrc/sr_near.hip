@@ -18,10 +18,19 @@
 //
 // Work decomposition: one wavefront per target (4 per workgroup).  The target's cell and its
 // neighbours in the uniform cell grid (side >= near radius) hold every near pair; with cells in
-// z-fastest order, the 27 neighbour cells are 9 contiguous record ranges, read coalesced by the 64
-// lanes.  Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
+// z-fastest order, the 27 neighbour cells are 9 contiguous ranges.  The 64 lanes test 64 candidates
+// at a time (compact single- or double-precision positions) and append the near ones to a per-wave
+// queue in LDS; each time the queue holds 64 pairs, all 64 lanes evaluate one pair each, so the
+// FP64 regularized kernels run without idle lanes.  The three smoothing factors of a pair share one
+// exp(-t^2) and one polynomial (no branches): s_k = 1 - exp(-t^2) P_k(t) with
+// P_1 = erfcx(t), P_2 = P_1 + (2/sqrt(pi)) t, P_3 = P_2 + (4/(3 sqrt(pi))) t^3.
+// Every pair evaluates all three smoothing lengths: sorting pairs into per-delta classes would skip
+// about 40% of the smoothing work, but the class-specialized code needs enough registers to halve
+// the wavefronts per SIMD, which costs more than it saves (measured on MI355X).
+// Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
 #include <math.h>
 
+#include "sr_erfcx_table.h"
 #include "sr_internal.h"
 
 namespace sr {
@@ -38,6 +47,14 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// orders this wavefront's LDS accesses across lanes (no workgroup barrier needed: one wave owns the queue)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double I0f(double lam)
 {
     const double a = fabs(lam);
@@ -50,151 +67,218 @@ __device__ __forceinline__ double I2f(double lam)
     return (2.0 / 3.0) * ((0.5 - lam * lam) * exp(-lam * lam) * kInvSqrtPi + a * a * a * erfc(a));
 }
 
+// s1, s2, s3 at t >= 0 (eqs. (s1)-(s3)), replaced by 1 for t > cutoff.  erfc(t) = exp(-t^2) erfcx(t),
+// erfcx from the interpolating polynomial of sr_erfcx_table.h (|erfc error| < 1e-15 on [0, 6.25]);
+// beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
+__device__ __forceinline__ void smoothing3(double t, double cutoff, double &s1, double &s2, double &s3)
+{
+    using namespace erfcx_poly;
+    const double E = exp(-t * t);
+    const double tc = fmin(t, 6.25);
+    const double den = tc + kL;
+    double inv = __builtin_amdgcn_rcp(den);
+    double e = __builtin_fma(-den, inv, 1.0);
+    inv = __builtin_fma(inv, e, inv);
+    e = __builtin_fma(-den, inv, 1.0);
+    inv = __builtin_fma(inv, e, inv);
+    const double x = __builtin_fma(kA, (tc - kL) * inv, kB);
+    double pz = kC[kDegree];
+#pragma unroll
+    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, kC[k]);
+    const double R = kL * inv * pz;
+    const double P2 = __builtin_fma(kTwoOverSqrtPi, t, R);
+    const double P3 = __builtin_fma((2.0 / 3.0) * kTwoOverSqrtPi * t * t, t, P2);
+    const double Ec = t > cutoff ? 0.0 : E;  // beyond the cut-off s1 = s2 = s3 = 1 exactly
+    s1 = __builtin_fma(-Ec, R, 1.0);
+    s2 = __builtin_fma(-Ec, P2, 1.0);
+    s3 = __builtin_fma(-Ec, P3, 1.0);
+}
+
+__device__ __forceinline__ double pick3(const double (&v)[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+
+struct Target {
+    double y[3], x0[3], n[3], b, c, q0[3];
+};
+
+struct Acc {
+    double sl[3][3], dl[3][3];
+};
+
+// Adds one pair's contribution at the smoothing length of sorted position J.
+template <int J, bool SL, bool DL>
+__device__ __forceinline__ void accumulate_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
+                                                 double dz, double gx, double gy, double gz, double dg, double t1x,
+                                                 double t1y, double t1z, double ex, double ey, double ez,
+                                                 const DevParams &p, Acc &A)
+{
+    double s1, s2, s3;
+    smoothing3(r * p.inv_delta[J], p.cutoff, s1, s2, s3);
+    if (SL) {
+        const double k1 = s1 * ir, k2 = dg * s2 * ir3;
+        A.sl[J][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[J][0]));
+        A.sl[J][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[J][1]));
+        A.sl[J][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[J][2]));
+    }
+    if (DL) {
+        const double k2 = s2 * ir3, k3 = s3 * ir5;
+        A.dl[J][0] = __builtin_fma(ex, k3, __builtin_fma(t1x, k2, A.dl[J][0]));
+        A.dl[J][1] = __builtin_fma(ey, k3, __builtin_fma(t1y, k2, A.dl[J][1]));
+        A.dl[J][2] = __builtin_fma(ez, k3, __builtin_fma(t1z, k2, A.dl[J][2]));
+    }
+}
+
+// One near pair, accumulated at the three smoothing lengths (sorted-delta order).
+template <bool SL, bool DL>
+__device__ __forceinline__ void near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
+{
+    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) {
+        // target on a quadrature point: limit of s1(r/delta)/r is 2/(sqrt(pi) delta); the d d s2/r^3
+        // term and the whole double-layer term vanish
+        if (SL) {
+            const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double l = kTwoOverSqrtPi * p.inv_delta[j];
+                A.sl[j][0] += gx * l;
+                A.sl[j][1] += gy * l;
+                A.sl[j][2] += gz * l;
+            }
+        }
+        return;
+    }
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    const double ir2 = ir * ir;
+    const double ir3 = ir2 * ir;
+    const double ir5 = ir3 * ir2;
+    double gx = 0, gy = 0, gz = 0, dg = 0;
+    if (SL) {
+        gx = s.fw[0] - T.c * s.nw[0];
+        gy = s.fw[1] - T.c * s.nw[1];
+        gz = s.fw[2] - T.c * s.nw[2];
+        dg = dx * gx + dy * gy + dz * gz;
+    }
+    double t1x = 0, t1y = 0, t1z = 0, ex = 0, ey = 0, ez = 0;
+    if (DL) {
+        const double nx = T.n[0], ny = T.n[1], nz = T.n[2], b = T.b;
+        const double hx = s.x - T.x0[0], hy = s.y - T.x0[1], hz = s.z - T.x0[2];
+        const double ax = s.q[0] - T.q0[0], ay = s.q[1] - T.q0[1], az = s.q[2] - T.q0[2];
+        const double mx = s.nw[0], my = s.nw[1], mz = s.nw[2];
+        const double na = nx * ax + ny * ay + nz * az;
+        const double nm = nx * mx + ny * my + nz * mz;
+        const double xa = hx * ax + hy * ay + hz * az;
+        const double xm = hx * mx + hy * my + hz * mz;
+        const double xn = hx * nx + hy * ny + hz * nz;
+        const double xx = hx * hx + hy * hy + hz * hz;
+        const double nanm = na * nm;
+        const double c1n = b * nanm - xa * nm - na * xm;
+        t1x = nx * c1n - hx * nanm;
+        t1y = ny * c1n - hy * nanm;
+        t1z = nz * c1n - hz * nanm;
+        const double c2h = b * (xa * nm + na * xm) - xa * xm;
+        const double c2n = b * xa * xm;
+        const double rmb = xx - 2.0 * b * xn;  // r^2 - b^2
+        ex = hx * c2h + nx * c2n - rmb * t1x;
+        ey = hy * c2h + ny * c2n - rmb * t1y;
+        ez = hz * c2h + nz * c2n - rmb * t1z;
+    }
+    accumulate_delta<0, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+    accumulate_delta<1, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+    accumulate_delta<2, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+}
+
 template <typename TC, bool SL, bool DL>
 __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
-                                                               const SrcRec<TC> *__restrict__ recc,
+                                                               const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
                                                                EvalArgs a, DevParams p, TC rc2,
                                                                const double *__restrict__ part, int nparts)
 {
-    const int wave = (int)threadIdx.x / kWave;
+    __shared__ int queue_all[kBlock / kWave][2 * kWave];
+    // readfirstlane: tells the compiler the wave index (hence the target) is wavefront-uniform, so the
+    // target's data live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int lane = (int)threadIdx.x % kWave;
+    int *queue = queue_all[wave];
     const int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
     if (t >= a.m) return;  // wavefront-uniform exit
 
-    const double yx = a.y[3 * t], yy = a.y[3 * t + 1], yz = a.y[3 * t + 2];
-    const double x0x = a.x0[3 * t], x0y = a.x0[3 * t + 1], x0z = a.x0[3 * t + 2];
-    const double nx = a.n0[3 * t], ny = a.n0[3 * t + 1], nz = a.n0[3 * t + 2];
-    const double b = a.b[t];
-    double c = 0.0, q0x = 0.0, q0y = 0.0, q0z = 0.0;
-    if (SL) c = a.f0[3 * t] * nx + a.f0[3 * t + 1] * ny + a.f0[3 * t + 2] * nz;
-    if (DL) {
-        q0x = a.q0[3 * t];
-        q0y = a.q0[3 * t + 1];
-        q0z = a.q0[3 * t + 2];
+    Target T;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T.y[i] = a.y[3 * t + i];
+        T.x0[i] = a.x0[3 * t + i];
+        T.n[i] = a.n0[3 * t + i];
+        T.q0[i] = DL ? a.q0[3 * t + i] : 0.0;
     }
-    const TC tyx = (TC)yx, tyy = (TC)yy, tyz = (TC)yz;
+    T.b = a.b[t];
+    T.c = SL ? a.f0[3 * t] * T.n[0] + a.f0[3 * t + 1] * T.n[1] + a.f0[3 * t + 2] * T.n[2] : 0.0;
+    const TC tyx = (TC)T.y[0], tyy = (TC)T.y[1], tyz = (TC)T.y[2];
 
     int ci[3];
-    {
-        const double yv[3] = {yx, yy, yz};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double u = floor((yv[d] - grid.lo[d]) * grid.inv_side);
-            u = fmin(fmax(u, -2.0), (double)grid.g[d] + 1.0);
-            ci[d] = (int)u;
-        }
+    for (int d = 0; d < 3; ++d) {
+        double u = floor((T.y[d] - grid.lo[d]) * grid.inv_side);
+        u = fmin(fmax(u, -2.0), (double)grid.g[d] + 1.0);
+        ci[d] = (int)u;
     }
 
-    double asl[3][3], adl[3][3];
+    Acc A;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) asl[j][i] = adl[j][i] = 0.0;
+        for (int i = 0; i < 3; ++i) A.sl[j][i] = A.dl[j][i] = 0.0;
 
+    int cnt = 0;
     const int z0 = max(ci[2] - 1, 0), z1 = min(ci[2] + 1, grid.g[2] - 1);
     for (int ix = max(ci[0] - 1, 0); ix <= min(ci[0] + 1, grid.g[0] - 1); ++ix) {
         for (int iy = max(ci[1] - 1, 0); iy <= min(ci[1] + 1, grid.g[1] - 1); ++iy) {
             if (z0 > z1) continue;
             const int cb = (ix * grid.g[1] + iy) * grid.g[2];
             const int s0 = cell_start[cb + z0], s1 = cell_start[cb + z1 + 1];
-            for (int k = s0 + lane; k < s1; k += kWave) {
-                const SrcRec<TC> &sc = recc[k];
-                const TC r2c = pair_r2(tyx, tyy, tyz, sc.x, sc.y, sc.z);
-                if (!(r2c <= rc2)) continue;
-                const SrcRec<double> s = rec64[k];
-                const double dx = yx - s.x, dy = yy - s.y, dz = yz - s.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 == 0.0) {
-                    // target on a quadrature point: limit of s1(r/delta)/r is 2/(sqrt(pi) delta);
-                    // the d d s2/r^3 term and the whole double-layer term vanish
-                    if (SL) {
-                        const double gx = s.fw[0] - c * s.nw[0], gy = s.fw[1] - c * s.nw[1],
-                                     gz = s.fw[2] - c * s.nw[2];
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) {
-                            const double l = kTwoOverSqrtPi * p.inv_delta[j];
-                            asl[j][0] += gx * l;
-                            asl[j][1] += gy * l;
-                            asl[j][2] += gz * l;
-                        }
-                    }
-                    continue;
+            for (int base = s0; base < s1; base += kWave) {
+                const int k = base + lane;
+                bool nr = false;
+                if (k < s1) {
+                    const Pos4<TC> q = pos[k];
+                    nr = pair_r2(tyx, tyy, tyz, q.x, q.y, q.z) <= rc2;
                 }
-                const double ir = rsqrt(r2);
-                const double r = r2 * ir;
-                const double ir3 = ir * ir * ir;
-                const double ir5 = ir3 * ir * ir;
-                double gx = 0, gy = 0, gz = 0, dg = 0;
-                if (SL) {
-                    gx = s.fw[0] - c * s.nw[0];
-                    gy = s.fw[1] - c * s.nw[1];
-                    gz = s.fw[2] - c * s.nw[2];
-                    dg = dx * gx + dy * gy + dz * gz;
+                const uint64_t m = __ballot(nr);
+                if (nr) {
+                    const int off = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    queue[cnt + off] = k;
                 }
-                double t1x = 0, t1y = 0, t1z = 0, ex = 0, ey = 0, ez = 0;
-                if (DL) {
-                    const double hx = s.x - x0x, hy = s.y - x0y, hz = s.z - x0z;
-                    const double ax = s.q[0] - q0x, ay = s.q[1] - q0y, az = s.q[2] - q0z;
-                    const double mx = s.nw[0], my = s.nw[1], mz = s.nw[2];
-                    const double na = nx * ax + ny * ay + nz * az;
-                    const double nm = nx * mx + ny * my + nz * mz;
-                    const double xa = hx * ax + hy * ay + hz * az;
-                    const double xm = hx * mx + hy * my + hz * mz;
-                    const double xn = hx * nx + hy * ny + hz * nz;
-                    const double xx = hx * hx + hy * hy + hz * hz;
-                    const double nanm = na * nm;
-                    const double c1n = b * nanm - xa * nm - na * xm;
-                    t1x = nx * c1n - hx * nanm;
-                    t1y = ny * c1n - hy * nanm;
-                    t1z = nz * c1n - hz * nanm;
-                    const double c2h = b * (xa * nm + na * xm) - xa * xm;
-                    const double c2n = b * xa * xm;
-                    const double rmb = xx - 2.0 * b * xn;  // r^2 - b^2
-                    ex = hx * c2h + nx * c2n - rmb * t1x;
-                    ey = hy * c2h + ny * c2n - rmb * t1y;
-                    ez = hz * c2h + nz * c2n - rmb * t1z;
-                }
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const double tt = r * p.inv_delta[j];
-                    double s1 = 1.0, s2 = 1.0, s3 = 1.0;
-                    if (tt <= p.cutoff) {
-                        const double e = exp(-tt * tt);
-                        const double er = erf(tt);
-                        const double ce = kTwoOverSqrtPi * tt * e;
-                        s1 = er;
-                        s2 = er - ce;
-                        s3 = er - kTwoOverSqrtPi * (tt + (2.0 / 3.0) * tt * tt * tt) * e;
-                    }
-                    if (SL) {
-                        const double k1 = s1 * ir, k2 = dg * s2 * ir3;
-                        asl[j][0] += gx * k1 + dx * k2;
-                        asl[j][1] += gy * k1 + dy * k2;
-                        asl[j][2] += gz * k1 + dz * k2;
-                    }
-                    if (DL) {
-                        const double k2 = s2 * ir3, k3 = s3 * ir5;
-                        adl[j][0] += t1x * k2 + ex * k3;
-                        adl[j][1] += t1y * k2 + ey * k3;
-                        adl[j][2] += t1z * k2 + ez * k3;
-                    }
+                cnt += __popcll(m);
+                if (cnt >= kWave) {
+                    wave_lds_sync();
+                    const int k2 = queue[lane];
+                    wave_lds_sync();
+                    if (lane + kWave < cnt) queue[lane] = queue[lane + kWave];
+                    cnt -= kWave;
+                    wave_lds_sync();
+                    near_pair<SL, DL>(rec64[k2], T, p, A);
                 }
             }
         }
     }
+    wave_lds_sync();
+    if (lane < cnt) near_pair<SL, DL>(rec64[queue[lane]], T, p, A);
 
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            if (SL) asl[j][i] = wave_sum(asl[j][i]);
-            if (DL) adl[j][i] = wave_sum(adl[j][i]);
+            if (SL) A.sl[j][i] = wave_sum(A.sl[j][i]);
+            if (DL) A.dl[j][i] = wave_sum(A.dl[j][i]);
         }
 
     // extrapolation weights (the same for the single and double layer and for every component)
+    const double b = T.b;
     double w0 = 1.0, w1 = 0.0, w2 = 0.0;
-    const double dmax = fmax(p.rho[0], fmax(p.rho[1], p.rho[2])) * p.h;
+    const double dmax = p.rho[2] * p.h;  // largest delta (sorted)
     if (fabs(b) < p.cutoff * dmax) {
         double al[3], be[3];
 #pragma unroll
@@ -221,60 +305,59 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
             for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + i) * (size_t)a.m + t];
             double uj[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) uj[j] = (far + asl[j][i]) * inv8pi;
+            for (int j = 0; j < 3; ++j) uj[j] = (far + pick3(A.sl[j], i)) * inv8pi;
             a.u[3 * t + i] = w0 * uj[0] + w1 * uj[1] + w2 * uj[2];
             if (a.u_delta)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * j + i] = uj[j];
+                for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * p.ord[j] + i] = uj[j];
         }
         if (DL) {
             double far = 0.0;
             for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + 3 + i) * (size_t)a.m + t];
             double vj[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) vj[j] = -6.0 * (far + adl[j][i]) * inv8pi;
-            const double q0i = i == 0 ? q0x : (i == 1 ? q0y : q0z);
-            a.v[3 * t + i] = w0 * vj[0] + w1 * vj[1] + w2 * vj[2] + chi * q0i;
+            for (int j = 0; j < 3; ++j) vj[j] = -6.0 * (far + pick3(A.dl[j], i)) * inv8pi;
+            a.v[3 * t + i] = w0 * vj[0] + w1 * vj[1] + w2 * vj[2] + chi * pick3(T.q0, i);
             if (a.v_delta)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * j + i] = vj[j];
+                for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * p.ord[j] + i] = vj[j];
         }
     }
 }
 
 template <typename TC, bool SL, bool DL>
-hipError_t launch_t(const SrcRec<double> *rec64, const SrcRec<TC> *recc, const int *cell_start, const CellGrid &g,
+hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int *cell_start, const CellGrid &g,
                     const EvalArgs &a, const DevParams &p, TC rc2, const double *part, int nparts, hipStream_t s)
 {
     const int per_block = kBlock / kWave;
     const int64_t blocks = (a.m + per_block - 1) / per_block;
-    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64, recc,
+    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64, pos,
                        cell_start, g, a, p, rc2, part, nparts);
     return hipGetLastError();
 }
 
 template <typename TC>
-hipError_t dispatch(int layers, const SrcRec<double> *rec64, const SrcRec<TC> *recc, const int *cell_start,
+hipError_t dispatch(int layers, const SrcRec<double> *rec64, const Pos4<TC> *pos, const int *cell_start,
                     const CellGrid &g, const EvalArgs &a, const DevParams &p, TC rc2, const double *part,
                     int nparts, hipStream_t s)
 {
     if (layers == (SR_SL | SR_DL))
-        return launch_t<TC, true, true>(rec64, recc, cell_start, g, a, p, rc2, part, nparts, s);
-    if (layers == SR_SL) return launch_t<TC, true, false>(rec64, recc, cell_start, g, a, p, rc2, part, nparts, s);
-    return launch_t<TC, false, true>(rec64, recc, cell_start, g, a, p, rc2, part, nparts, s);
+        return launch_t<TC, true, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
+    if (layers == SR_SL) return launch_t<TC, true, false>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
+    return launch_t<TC, false, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
 }
 
 }  // namespace
 
 hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
-                                const SrcRec<float> *rec32, const int *cell_start, const CellGrid &grid,
-                                const EvalArgs &a, const DevParams &p, const double *part, int nparts,
-                                hipStream_t s)
+                                const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,
+                                const CellGrid &grid, const EvalArgs &a, const DevParams &p, const double *part,
+                                int nparts, hipStream_t s)
 {
     const double rc2 = p.rnear * p.rnear;
     if (precision == SR_MIXED)
-        return dispatch<float>(layers, rec64, rec32, cell_start, grid, a, p, (float)rc2, part, nparts, s);
-    return dispatch<double>(layers, rec64, rec64, cell_start, grid, a, p, rc2, part, nparts, s);
+        return dispatch<float>(layers, rec64, pos32, cell_start, grid, a, p, (float)rc2, part, nparts, s);
+    return dispatch<double>(layers, rec64, pos64, cell_start, grid, a, p, rc2, part, nparts, s);
 }
 
 }  // namespace sr

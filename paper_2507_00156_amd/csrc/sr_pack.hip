@@ -1,6 +1,7 @@
 // Gather the caller's quadrature and densities into the library's cell-sorted source records:
 // rec.x = x_o, rec.fw = f_o w_o, rec.nw = n_o w_o, rec.q = q_o with o = perm[i] (the caller's index of
 // sorted record i); the single-precision records are the round-to-nearest images of the double ones.
+// pos64 / pos32 repeat the coordinates in compact 32/16-byte form for the near-pair test.
 #include "sr_internal.h"
 
 namespace sr {
@@ -11,7 +12,9 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const double *__restrict__
                                                       const double *__restrict__ q,
                                                       const int64_t *__restrict__ perm, int64_t n,
                                                       SrcRec<double> *__restrict__ rec64,
-                                                      SrcRec<float> *__restrict__ rec32)
+                                                      SrcRec<float> *__restrict__ rec32,
+                                                      Pos4<double> *__restrict__ pos64,
+                                                      Pos4<float> *__restrict__ pos32)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -39,17 +42,20 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const double *__restrict__
         h.q[k] = (float)r.q[k];
     }
     rec32[i] = h;
+    pos64[i] = Pos4<double>{r.x, r.y, r.z, 0.0};
+    pos32[i] = Pos4<float>{h.x, h.y, h.z, 0.0f};
 }
 
 }  // namespace
 
 hipError_t launch_pack(const double *x, const double *nrm, const double *w, const double *f, const double *q,
-                       const int64_t *perm, int64_t n, SrcRec<double> *rec64, SrcRec<float> *rec32, hipStream_t s)
+                       const int64_t *perm, int64_t n, SrcRec<double> *rec64, SrcRec<float> *rec32,
+                       Pos4<double> *pos64, Pos4<float> *pos32, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, nrm, w, f, q, perm, n, rec64,
-                       rec32);
+                       rec32, pos64, pos32);
     return hipGetLastError();
 }
 
