@@ -54,7 +54,7 @@ typedef enum {
 enum { SR_SL = 1, SR_DL = 2 };
 
 /* Far-field precision.  SR_FP64: every sum in double.  SR_MIXED: far-field pair kernels in single
- * precision with double accumulation of 64-pair partial sums; the near regularized sums, the
+ * precision with double accumulation of 32-pair partial sums; the near regularized sums, the
  * far/near bookkeeping and the extrapolation stay in double. */
 enum { SR_FP64 = 0, SR_MIXED = 1 };
 

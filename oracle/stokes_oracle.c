@@ -290,3 +290,300 @@ void orc_set_num_threads(int nt)
     (void)nt;
 #endif
 }
+
+/* ------------------------------------------------------------------------------------------------
+ * Treecode far field, paper section 3.4 (kernel-independent treecode with barycentric Lagrange
+ * interpolation at Chebyshev points), evaluated literally per target as the paper describes: start
+ * at the root; if the MAC r_c / R <= theta holds the cluster interacts through its Chebyshev proxy
+ * points (eq. (particle-cluster-KITC)) with the ORIGINAL kernels; otherwise a leaf is summed
+ * directly with the regularized kernels for the three deltas (t > 6 -> s = 1), and a non-leaf is
+ * replaced by its children.  Then the 3x3 extrapolation as in orc_sl / orc_dl.
+ *
+ * Readings of points the paper leaves open (also in the design notes):
+ *   - octree: a cluster with more than N0 points is split at the midpoint of its box into 8
+ *     octants (a point goes to the upper half of an axis when x >= mid); empty octants are dropped;
+ *     every cluster's box is the bounding box of its points; children are visited in octant order
+ *     (bit 0: x upper, bit 1: y upper, bit 2: z upper);
+ *   - cluster radius r_c = half the box diagonal, R = distance from the target to the box centre;
+ *   - the MAC additionally requires the box to lie farther than the near radius 6 max_j delta_j
+ *     from the target (squared distance to the box > (6 max delta)^2); otherwise pairs that need
+ *     regularization would be approximated with the singular kernels.  The MAC is evaluated on
+ *     squared quantities: r_c^2 <= theta^2 R^2;
+ *   - Chebyshev points of the second kind s_k = c + (h/2) cos(k pi / p), k = 0..p per axis, with the
+ *     barycentric weights (-1)^k, halved at k = 0 and k = p; a coordinate equal to a node gets
+ *     L = 1 there and 0 elsewhere; an axis of zero extent puts all weight on k = 0;
+ *   - modified weights for the 15 channels f w (3), n w (3), q_j n_k w (9); the single layer uses
+ *     F - (f(x0).n0) N, the double layer Q - q(x0) (x) N (eq. (mod_weights) and the text after it).
+ * ------------------------------------------------------------------------------------------------ */
+#include <stdlib.h>
+
+typedef struct {
+    int64_t begin, end;    /* range in the tree-ordered point array */
+    double lo[3], hi[3];   /* bounding box of the cluster's points */
+    int child[8], nchild;
+} orc_node;
+
+typedef struct {
+    orc_node *nodes;
+    int nnodes, cap;
+    int64_t *order;        /* tree order -> caller index */
+} orc_tree_t;
+
+static int tree_push(orc_tree_t *T)
+{
+    if (T->nnodes == T->cap) {
+        T->cap = T->cap ? 2 * T->cap : 64;
+        T->nodes = (orc_node *)realloc(T->nodes, sizeof(orc_node) * (size_t)T->cap);
+    }
+    memset(&T->nodes[T->nnodes], 0, sizeof(orc_node));
+    return T->nnodes++;
+}
+
+static void tree_bbox(orc_tree_t *T, const double *x, int id)
+{
+    orc_node *nd = &T->nodes[id];
+    for (int d = 0; d < 3; ++d) {
+        nd->lo[d] = INFINITY;
+        nd->hi[d] = -INFINITY;
+    }
+    for (int64_t i = nd->begin; i < nd->end; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double v = x[3 * T->order[i] + d];
+            if (v < nd->lo[d]) nd->lo[d] = v;
+            if (v > nd->hi[d]) nd->hi[d] = v;
+        }
+}
+
+static void tree_split(orc_tree_t *T, const double *x, int id, int64_t leaf)
+{
+    if (T->nodes[id].end - T->nodes[id].begin <= leaf) return;
+    double mid[3];
+    for (int d = 0; d < 3; ++d) mid[d] = (T->nodes[id].lo[d] + T->nodes[id].hi[d]) * 0.5;
+    int64_t b = T->nodes[id].begin, e = T->nodes[id].end;
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(e - b));
+    int64_t cnt[8] = {0};
+    for (int64_t i = b; i < e; ++i) {
+        const double *p = x + 3 * T->order[i];
+        int oct = (p[0] >= mid[0]) | ((p[1] >= mid[1]) << 1) | ((p[2] >= mid[2]) << 2);
+        cnt[oct]++;
+    }
+    int64_t start[8], fill[8];
+    start[0] = 0;
+    for (int o = 1; o < 8; ++o) start[o] = start[o - 1] + cnt[o - 1];
+    for (int o = 0; o < 8; ++o) fill[o] = start[o];
+    for (int64_t i = b; i < e; ++i) {
+        const double *p = x + 3 * T->order[i];
+        int oct = (p[0] >= mid[0]) | ((p[1] >= mid[1]) << 1) | ((p[2] >= mid[2]) << 2);
+        tmp[fill[oct]++] = T->order[i];
+    }
+    memcpy(T->order + b, tmp, sizeof(int64_t) * (size_t)(e - b));
+    free(tmp);
+    for (int o = 0; o < 8; ++o) {
+        if (cnt[o] == 0) continue;
+        int c = tree_push(T);
+        T->nodes[c].begin = b + start[o];
+        T->nodes[c].end = b + start[o] + cnt[o];
+        tree_bbox(T, x, c);
+        T->nodes[id].child[T->nodes[id].nchild++] = c;
+    }
+    for (int k = 0; k < T->nodes[id].nchild; ++k) tree_split(T, x, T->nodes[id].child[k], leaf);
+}
+
+/* barycentric Lagrange basis L_0..L_p at coordinate v for the Chebyshev points of [lo, hi] */
+static void lagrange_1d(double v, double lo, double hi, int p, double *L)
+{
+    if (hi == lo) {
+        for (int k = 0; k <= p; ++k) L[k] = k == 0 ? 1.0 : 0.0;
+        return;
+    }
+    double c = 0.5 * (lo + hi), hw = 0.5 * (hi - lo), den = 0.0;
+    for (int k = 0; k <= p; ++k) {
+        double s = c + hw * cos(k * PI / p);
+        if (v == s) {
+            for (int j = 0; j <= p; ++j) L[j] = j == k ? 1.0 : 0.0;
+            return;
+        }
+        double wk = ((k & 1) ? -1.0 : 1.0) * ((k == 0 || k == p) ? 0.5 : 1.0);
+        L[k] = wk / (v - s);
+        den += L[k];
+    }
+    for (int k = 0; k <= p; ++k) L[k] /= den;
+}
+
+/* regularized single and double layer of one source at the three deltas (the sums of orc_sl_delta
+ * and orc_dl_delta for one pair), added to us[j][i], vs[j][i] before the 1/(8 pi) factor */
+static void pair_regularized(const double *yt, const double *x0t, const double *nn, double bb, double c,
+                             const double *q0t, const double *xp, const double *np_, double wp, const double *fp,
+                             const double *qp, double h, const double rho[3], double us[3][3], double vs[3][3])
+{
+    double d[3], g[3], xh[3], a[3], mw[3];
+    for (int k = 0; k < 3; ++k) {
+        d[k] = yt[k] - xp[k];
+        g[k] = (fp[k] - c * np_[k]) * wp;
+        xh[k] = xp[k] - x0t[k];
+        a[k] = qp[k] - q0t[k];
+        mw[k] = np_[k] * wp;
+    }
+    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int jd = 0; jd < 3; ++jd) {
+        double delta = rho[jd] * h;
+        if (r == 0.0) {
+            for (int i = 0; i < 3; ++i) us[jd][i] += 2.0 / (sqrt(PI) * delta) * g[i];
+            continue;
+        }
+        double s[3];
+        orc_smoothing(r / delta, s);
+        double r3 = r * r * r, r5 = r3 * r * r;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                us[jd][i] += ((i == j ? 1.0 : 0.0) * s[0] / r + d[i] * d[j] * s[1] / r3) * g[j];
+                for (int k = 0; k < 3; ++k) {
+                    double t1 = bb * nn[i] * nn[j] * nn[k]
+                              - (xh[i] * nn[j] * nn[k] + nn[i] * xh[j] * nn[k] + nn[i] * nn[j] * xh[k]);
+                    double t2 = bb * (xh[i] * xh[j] * nn[k] + xh[i] * nn[j] * xh[k] + nn[i] * xh[j] * xh[k])
+                              - xh[i] * xh[j] * xh[k];
+                    vs[jd][i] += -6.0 * (t1 * s[1] / r3 + (t2 - (r * r - bb * bb) * t1) * s[2] / r5) * a[j] * mw[k];
+                }
+            }
+    }
+}
+
+typedef struct {
+    const double *x, *nrm, *w, *f, *q;
+    const orc_tree_t *T;
+    const double *mw;  /* modified weights: [node][proxy][15] */
+    int p;
+    double theta, rnear, h, rho[3];
+} tree_ctx;
+
+static void tree_visit(const tree_ctx *C, int id, const double *yt, const double *x0t, const double *nn, double bb,
+                       double c, const double *q0t, double us[3][3], double vs[3][3])
+{
+    const orc_node *nd = &C->T->nodes[id];
+    /* MAC: r_c <= theta R, and the whole box farther than the near radius */
+    double rc2 = 0.0, R2 = 0.0, g2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double e = nd->hi[d] - nd->lo[d];
+        rc2 += 0.25 * e * e;
+        double dc = yt[d] - 0.5 * (nd->lo[d] + nd->hi[d]);
+        R2 += dc * dc;
+        double gap = nd->lo[d] - yt[d] > 0.0 ? nd->lo[d] - yt[d] : (yt[d] - nd->hi[d] > 0.0 ? yt[d] - nd->hi[d] : 0.0);
+        g2 += gap * gap;
+    }
+    if (rc2 <= C->theta * C->theta * R2 && g2 > C->rnear * C->rnear) {
+        int np1 = C->p + 1;
+        const double *W = C->mw + (size_t)id * np1 * np1 * np1 * 15;
+        double su[3] = {0, 0, 0}, sv[3] = {0, 0, 0};
+        for (int k1 = 0; k1 <= C->p; ++k1)
+            for (int k2 = 0; k2 <= C->p; ++k2)
+                for (int k3 = 0; k3 <= C->p; ++k3) {
+                    int kk[3] = {k1, k2, k3};
+                    double s[3], d[3];
+                    for (int dd = 0; dd < 3; ++dd) {
+                        double cc = 0.5 * (nd->lo[dd] + nd->hi[dd]), hw = 0.5 * (nd->hi[dd] - nd->lo[dd]);
+                        s[dd] = nd->hi[dd] == nd->lo[dd] ? nd->lo[dd] : cc + hw * cos(kk[dd] * PI / C->p);
+                        d[dd] = yt[dd] - s[dd];
+                    }
+                    const double *g = W + ((size_t)(k1 * np1 + k2) * np1 + k3) * 15;
+                    double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    double r3 = r * r * r, r5 = r3 * r * r;
+                    /* single layer: S_ij (F_j - c N_j) */
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j)
+                            su[i] += ((i == j ? 1.0 : 0.0) / r + d[i] * d[j] / r3) * (g[j] - c * g[3 + j]);
+                    /* double layer: T_ijk (Q_jk - q0_j N_k) */
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j)
+                            for (int k = 0; k < 3; ++k)
+                                sv[i] += -6.0 * d[i] * d[j] * d[k] / r5 * (g[6 + 3 * j + k] - q0t[j] * g[3 + k]);
+                }
+        for (int jd = 0; jd < 3; ++jd)
+            for (int i = 0; i < 3; ++i) {
+                us[jd][i] += su[i];
+                vs[jd][i] += sv[i];
+            }
+        return;
+    }
+    if (nd->nchild == 0) {
+        for (int64_t i = nd->begin; i < nd->end; ++i) {
+            int64_t o = C->T->order[i];
+            pair_regularized(yt, x0t, nn, bb, c, q0t, C->x + 3 * o, C->nrm + 3 * o, C->w[o], C->f + 3 * o,
+                             C->q + 3 * o, C->h, C->rho, us, vs);
+        }
+        return;
+    }
+    for (int k = 0; k < nd->nchild; ++k) tree_visit(C, nd->child[k], yt, x0t, nn, bb, c, q0t, us, vs);
+}
+
+/* Treecode evaluation of both layers.  out_sl, out_dl: (m,3); optional out_*_delta (m,3,3).
+ * Returns the number of tree nodes, or -1 if an extrapolation system is singular. */
+int orc_tree(int64_t n, const double *x, const double *nrm, const double *w, const double *f, const double *q,
+             int64_t m, const double *y, const double *x0, const double *n0, const double *b, const double *f0,
+             const double *q0, double h, const double rho[3], int p, double theta, int64_t leaf, double *out_sl,
+             double *out_dl, double *out_sl_delta, double *out_dl_delta)
+{
+    orc_tree_t T = {0};
+    T.order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) T.order[i] = i;
+    int root = tree_push(&T);
+    T.nodes[root].begin = 0;
+    T.nodes[root].end = n;
+    tree_bbox(&T, x, root);
+    tree_split(&T, x, root, leaf);
+
+    /* modified weights, eq. (mod_weights), for every cluster */
+    int np1 = p + 1, nprox = np1 * np1 * np1;
+    double *mw = (double *)calloc((size_t)T.nnodes * nprox * 15, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int id = 0; id < T.nnodes; ++id) {
+        const orc_node *nd = &T.nodes[id];
+        double L[3][17];
+        for (int64_t i = nd->begin; i < nd->end; ++i) {
+            int64_t o = T.order[i];
+            for (int d = 0; d < 3; ++d) lagrange_1d(x[3 * o + d], nd->lo[d], nd->hi[d], p, L[d]);
+            double ch[15];
+            for (int j = 0; j < 3; ++j) {
+                ch[j] = f[3 * o + j] * w[o];
+                ch[3 + j] = nrm[3 * o + j] * w[o];
+            }
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k) ch[6 + 3 * j + k] = q[3 * o + j] * nrm[3 * o + k] * w[o];
+            for (int k1 = 0; k1 <= p; ++k1)
+                for (int k2 = 0; k2 <= p; ++k2)
+                    for (int k3 = 0; k3 <= p; ++k3) {
+                        double lk = L[0][k1] * L[1][k2] * L[2][k3];
+                        double *g = mw + ((size_t)id * nprox + (k1 * np1 + k2) * np1 + k3) * 15;
+                        for (int c = 0; c < 15; ++c) g[c] += lk * ch[c];
+                    }
+        }
+    }
+    double rmax = rho[0];
+    for (int j = 1; j < 3; ++j)
+        if (rho[j] > rmax) rmax = rho[j];
+    tree_ctx C = {x, nrm, w, f, q, &T, mw, p, theta, 6.0 * rmax * h, h, {rho[0], rho[1], rho[2]}};
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+    for (int64_t it = 0; it < m; ++it) {
+        double us[3][3] = {{0}}, vs[3][3] = {{0}};
+        const double *nn = n0 + 3 * it;
+        double c = f0[3 * it] * nn[0] + f0[3 * it + 1] * nn[1] + f0[3 * it + 2] * nn[2];
+        tree_visit(&C, root, y + 3 * it, x0 + 3 * it, nn, b[it], c, q0 + 3 * it, us, vs);
+        double ud[9], vd[9];
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                ud[3 * j + i] = us[j][i] / (8.0 * PI);
+                vd[3 * j + i] = vs[j][i] / (8.0 * PI);
+            }
+        if (out_sl_delta) memcpy(out_sl_delta + 9 * it, ud, sizeof ud);
+        if (out_dl_delta) memcpy(out_dl_delta + 9 * it, vd, sizeof vd);
+        if (orc_extrapolate(b[it], h, rho, ud, out_sl + 3 * it)) bad |= 1;
+        if (orc_extrapolate(b[it], h, rho, vd, out_dl + 3 * it)) bad |= 1;
+        double chi = b[it] < 0.0 ? 1.0 : (b[it] > 0.0 ? 0.0 : 0.5);
+        for (int i = 0; i < 3; ++i) out_dl[3 * it + i] += chi * q0[3 * it + i];
+    }
+    int nn_ = T.nnodes;
+    free(mw);
+    free(T.nodes);
+    free(T.order);
+    return bad ? -1 : nn_;
+}

@@ -11,7 +11,7 @@
 //     the scalar data cache and feeds the VALU as scalar operands: no LDS traffic, no barriers;
 //   - near pairs (r^2 <= rc2 by the shared pair_r2 test) are selected out (not multiplied by zero:
 //     r can be 0);
-//   - mixed precision: pair kernels in FP32, 64-pair FP32 partial sums promoted to FP64;
+//   - mixed precision: pair kernels in FP32, 32-pair FP32 partial sums promoted to FP64;
 //   - output: per-split partial sums part[split][channel][target], channel 0..2 = single-layer
 //     sum of S g, channel 3..5 = sum of d (d.a)(d.m) / r^5 (the -6 and 1/(8 pi) are applied
 //     when the near-field kernel combines the parts).
@@ -20,7 +20,7 @@
 namespace sr {
 namespace {
 
-constexpr int kTile = 64;  // FP32 partial-sum length before promotion to FP64
+constexpr int kTile = 32;  // FP32 partial-sum length before promotion to FP64
 
 __device__ __forceinline__ float rsqrt_t(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_t(double v) { return rsqrt(v); }
