@@ -302,6 +302,7 @@ void orc_set_num_threads(int nt)
  * Readings of points the paper leaves open (also in the design notes):
  *   - octree: a cluster with more than N0 points is split at the midpoint of its box into 8
  *     octants (a point goes to the upper half of an axis when x >= mid); empty octants are dropped;
+ *     a cluster whose points all coincide (one octant only) is not split;
  *     every cluster's box is the bounding box of its points; children are visited in octant order
  *     (bit 0: x upper, bit 1: y upper, bit 2: z upper);
  *   - cluster radius r_c = half the box diagonal, R = distance from the target to the box centre;
@@ -366,6 +367,12 @@ static void tree_split(orc_tree_t *T, const double *x, int id, int64_t leaf)
         const double *p = x + 3 * T->order[i];
         int oct = (p[0] >= mid[0]) | ((p[1] >= mid[1]) << 1) | ((p[2] >= mid[2]) << 2);
         cnt[oct]++;
+    }
+    int nonempty = 0;
+    for (int o = 0; o < 8; ++o) nonempty += cnt[o] > 0;
+    if (nonempty < 2) { /* all points coincide: the cluster cannot be split and stays a leaf */
+        free(tmp);
+        return;
     }
     int64_t start[8], fill[8];
     start[0] = 0;

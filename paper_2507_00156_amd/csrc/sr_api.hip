@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "sr_internal.h"
+#include "sr_tree.h"
 
 using namespace sr;
 
@@ -106,6 +107,23 @@ struct sr_ctx {
     double grid_rnear = -1.0;
     bool layout_dirty = true, pack_dirty = true;
 
+    // treecode far field
+    TreeHost tree;
+    bool tree_dirty = true, tree_weights_dirty = true;
+    int tree_p = -1;
+    int64_t tree_leaf = -1;
+    DevBuf<TreeNode> t_nodes;
+    DevBuf<int> t_item_node, t_item_begin, t_item_end, t_node_item0, t_idx_in, t_order;
+    DevBuf<int64_t> t_perm;
+    DevBuf<SrcRec<double>> t_rec64;
+    DevBuf<SrcRec<float>> t_rec32;
+    DevBuf<ProxRec<double>> t_prox64;
+    DevBuf<ProxRec<float>> t_prox32;
+    DevBuf<double> t_partial;
+    DevBuf<uint32_t> t_key_in, t_key_out;
+    DevBuf<char> t_sort_tmp;
+    TreeDev tdev;
+
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;     // created events, reused
     std::vector<hipEvent_t> ev_recorded; // 3 per profiled evaluation: start, far done, near done
@@ -124,6 +142,22 @@ struct sr_ctx {
         pos64.release();
         pos32.release();
         part.release();
+        t_nodes.release();
+        t_item_node.release();
+        t_item_begin.release();
+        t_item_end.release();
+        t_node_item0.release();
+        t_idx_in.release();
+        t_order.release();
+        t_perm.release();
+        t_rec64.release();
+        t_rec32.release();
+        t_prox64.release();
+        t_prox32.release();
+        t_partial.release();
+        t_key_in.release();
+        t_key_out.release();
+        t_sort_tmp.release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev_recorded) (void)hipEventDestroy(e);
     }
@@ -219,6 +253,80 @@ sr_status ensure_packed(sr_ctx *c, hipStream_t s)
     return SR_OK;
 }
 
+// Octree, proxy points and tree-ordered records for the treecode far field; modified weights when a
+// density changed.
+sr_status ensure_tree(sr_ctx *c, hipStream_t s)
+{
+    const int p = c->prm.tree_degree;
+    const int64_t leaf = c->prm.tree_leaf;
+    if (c->tree_dirty || c->tree_p != p || c->tree_leaf != leaf) {
+        TreeHost &T = c->tree;
+        build_tree(c->hx.data(), c->n, leaf, p, T);
+        const int nn = (int)T.nodes.size(), np1 = p + 1, nprox = np1 * np1 * np1, ni = (int)T.item_node.size();
+        SR_HIP(c->t_nodes.reserve(nn));
+        SR_HIP(c->t_item_node.reserve(ni));
+        SR_HIP(c->t_item_begin.reserve(ni));
+        SR_HIP(c->t_item_end.reserve(ni));
+        SR_HIP(c->t_node_item0.reserve(nn + 1));
+        SR_HIP(c->t_perm.reserve(c->n));
+        SR_HIP(c->t_rec64.reserve(c->n));
+        SR_HIP(c->t_rec32.reserve(c->n));
+        SR_HIP(c->t_prox64.reserve((size_t)nn * nprox));
+        SR_HIP(c->t_prox32.reserve((size_t)nn * nprox));
+        SR_HIP(c->t_partial.reserve((size_t)ni * nprox * 16));
+        std::vector<ProxRec<double>> p64((size_t)nn * nprox);
+        std::vector<ProxRec<float>> p32((size_t)nn * nprox);
+        for (size_t k = 0; k < p64.size(); ++k) {
+            p64[k] = ProxRec<double>{};
+            p32[k] = ProxRec<float>{};
+            p64[k].x = T.proxy_xyz[3 * k];
+            p64[k].y = T.proxy_xyz[3 * k + 1];
+            p64[k].z = T.proxy_xyz[3 * k + 2];
+            p32[k].x = (float)p64[k].x;
+            p32[k].y = (float)p64[k].y;
+            p32[k].z = (float)p64[k].z;
+        }
+        SR_HIP(hipMemcpyAsync(c->t_nodes.p, T.nodes.data(), nn * sizeof(TreeNode), hipMemcpyHostToDevice, s));
+        SR_HIP(hipMemcpyAsync(c->t_item_node.p, T.item_node.data(), ni * sizeof(int), hipMemcpyHostToDevice, s));
+        SR_HIP(hipMemcpyAsync(c->t_item_begin.p, T.item_begin.data(), ni * sizeof(int), hipMemcpyHostToDevice, s));
+        SR_HIP(hipMemcpyAsync(c->t_item_end.p, T.item_end.data(), ni * sizeof(int), hipMemcpyHostToDevice, s));
+        SR_HIP(hipMemcpyAsync(c->t_node_item0.p, T.node_item0.data(), (nn + 1) * sizeof(int), hipMemcpyHostToDevice,
+                              s));
+        SR_HIP(hipMemcpyAsync(c->t_perm.p, T.order.data(), c->n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        SR_HIP(hipMemcpyAsync(c->t_prox64.p, p64.data(), p64.size() * sizeof(ProxRec<double>), hipMemcpyHostToDevice,
+                              s));
+        SR_HIP(hipMemcpyAsync(c->t_prox32.p, p32.data(), p32.size() * sizeof(ProxRec<float>), hipMemcpyHostToDevice,
+                              s));
+        SR_HIP(hipStreamSynchronize(s));  // host staging vectors die at return
+        TreeDev &D = c->tdev;
+        D.nodes = c->t_nodes.p;
+        D.item_node = c->t_item_node.p;
+        D.item_begin = c->t_item_begin.p;
+        D.item_end = c->t_item_end.p;
+        D.node_item0 = c->t_node_item0.p;
+        D.trec64 = c->t_rec64.p;
+        D.trec32 = c->t_rec32.p;
+        D.prox64 = c->t_prox64.p;
+        D.prox32 = c->t_prox32.p;
+        D.nnodes = nn;
+        D.nitems = ni;
+        D.nprox = nprox;
+        D.p = p;
+        D.stack_cap = 7 * T.depth + 2;
+        c->tree_p = p;
+        c->tree_leaf = leaf;
+        c->tree_dirty = false;
+        c->tree_weights_dirty = true;
+    }
+    if (c->tree_weights_dirty) {
+        SR_HIP(launch_pack(c->x.p, c->nrm.p, c->w.p, c->have_sl ? c->f.p : nullptr, c->have_dl ? c->q.p : nullptr,
+                           c->t_perm.p, c->n, c->t_rec64.p, c->t_rec32.p, nullptr, nullptr, s));
+        SR_HIP(launch_anterp(c->tdev, c->tree.cosk.data(), c->t_partial.p, s));
+        c->tree_weights_dirty = false;
+    }
+    return SR_OK;
+}
+
 sr_status record_event(sr_ctx *c, hipStream_t s)
 {
     hipEvent_t e;
@@ -307,7 +415,6 @@ sr_status sr_set_params(sr_ctx *c, const sr_params *p)
         if (!(p->tree_theta >= 0.0 && p->tree_theta < 1.0))
             return fail(SR_EINVAL, "sr_set_params: tree_theta must be in [0, 1)");
         if (p->tree_leaf < 1) return fail(SR_EINVAL, "sr_set_params: tree_leaf must be >= 1");
-        return fail(SR_EINVAL, "sr_set_params: SR_TREE is not available in this build");
     }
     c->prm = *p;
     c->have_params = true;
@@ -347,6 +454,7 @@ sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nr
     c->have_sl = c->have_dl = false;
     c->layout_dirty = true;
     c->pack_dirty = true;
+    c->tree_dirty = true;
     return SR_OK;
 }
 
@@ -367,6 +475,7 @@ sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
     else
         c->have_dl = true;
     c->pack_dirty = true;
+    c->tree_weights_dirty = true;
     return SR_OK;
 }
 
@@ -421,12 +530,44 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     dp.rnear = c->grid_rnear;
     dp.precision = c->prm.precision;
 
-    SR_HIP(c->part.reserve((size_t)kFarSplits * 6 * (size_t)m));
+    const bool tree = c->prm.far_method == SR_TREE;
+    int nparts = kFarSplits;
+    if (tree) {
+        if ((st = ensure_tree(c, s)) != SR_OK) return st;
+        TreeDev &D = c->tdev;
+        SR_HIP(c->t_key_in.reserve(m));
+        SR_HIP(c->t_key_out.reserve(m));
+        SR_HIP(c->t_idx_in.reserve(m));
+        SR_HIP(c->t_order.reserve(m));
+        const size_t tb = target_sort_tmp_bytes((int)m);
+        SR_HIP(c->t_sort_tmp.reserve(tb));
+        D.key_in = c->t_key_in.p;
+        D.key_out = c->t_key_out.p;
+        D.idx_in = c->t_idx_in.p;
+        D.order = c->t_order.p;
+        D.sort_tmp = c->t_sort_tmp.p;
+        D.sort_tmp_bytes = c->t_sort_tmp.cap;
+        nparts = 1;
+    }
+    SR_HIP(c->part.reserve((size_t)nparts * 6 * (size_t)m));
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
-    SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, c->part.p, s));
+    if (tree) {
+        // Morton order over the sources' cell grid box, 1024 steps per axis
+        const TreeNode &root = c->tree.nodes[0];
+        double ext = 0.0;
+        double lo[3];
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = root.lo[d] - dp.rnear;
+            ext = std::max(ext, root.hi[d] - root.lo[d] + 2.0 * dp.rnear);
+        }
+        SR_HIP(launch_target_order(y, (int)m, lo, 1024.0 / ext, c->tdev, s));
+        SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear, c->part.p, s));
+    } else {
+        SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, c->part.p, s));
+    }
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p, c->cell_start.p,
-                                c->grid, a, dp, c->part.p, kFarSplits, s));
+                                c->grid, a, dp, c->part.p, nparts, s));
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     return SR_OK;
 }

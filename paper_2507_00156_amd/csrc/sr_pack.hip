@@ -1,7 +1,7 @@
 // Gather the caller's quadrature and densities into the library's cell-sorted source records:
 // rec.x = x_o, rec.fw = f_o w_o, rec.nw = n_o w_o, rec.q = q_o with o = perm[i] (the caller's index of
 // sorted record i); the single-precision records are the round-to-nearest images of the double ones.
-// pos64 / pos32 repeat the coordinates in compact 32/16-byte form for the near-pair test.
+// pos64 / pos32 (optional) repeat the coordinates in compact 32/16-byte form for the near-pair test.
 #include "sr_internal.h"
 
 namespace sr {
@@ -42,8 +42,8 @@ __global__ __launch_bounds__(kBlock) void pack_kernel(const double *__restrict__
         h.q[k] = (float)r.q[k];
     }
     rec32[i] = h;
-    pos64[i] = Pos4<double>{r.x, r.y, r.z, 0.0};
-    pos32[i] = Pos4<float>{h.x, h.y, h.z, 0.0f};
+    if (pos64) pos64[i] = Pos4<double>{r.x, r.y, r.z, 0.0};
+    if (pos32) pos32[i] = Pos4<float>{h.x, h.y, h.z, 0.0f};
 }
 
 }  // namespace
