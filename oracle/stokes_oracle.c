@@ -14,6 +14,8 @@
  *
  * Readings of points the paper leaves open (each also listed in the design notes):
  *   - cut-off: the smoothing factors are set to 1 only for t = r/delta > 6 (t == 6 is regularized);
+ *   - small t (< 0.2): s1, s2, s3 from their Maclaurin series (the printed differences cancel: s2 ~ t^3,
+ *     s3 ~ t^5); needed where two quadrature points of different families coincide up to rounding;
  *   - r == 0 (a target that coincides with a quadrature point): the single-layer kernel takes its
  *     limit delta_ij * 2/(sqrt(pi) delta); the double-layer term is 0 (x_hat = 0, b = 0, q - q0 = 0);
  *   - |b| >= 6 * max_j delta_j: every quadrature point is beyond the cut-off for every delta_j, so the
@@ -44,8 +46,27 @@ void orc_smoothing(double t, double s[3])
         s[0] = s[1] = s[2] = 1.0;
         return;
     }
-    double e = exp(-t * t);
     double c = 2.0 / sqrt(PI);
+    if (t < 0.2) {
+        /* The same functions from the Maclaurin series of erf and exp, free of the cancellation of
+         * the differences above (s2 ~ t^3, s3 ~ t^5):
+         *   s1 = c sum_n (-1)^n t^(2n+1) / (n! (2n+1))
+         *   s2 = c t^3 sum_n (-1)^n 2 t^(2n) / (n! (2n+3))
+         *   s3 = c t^5 sum_n (-1)^n 4 t^(2n) / (3 n! (2n+5))
+         * 12 terms: the next term is below 1e-20 relative for t < 0.2. */
+        double a1 = 0.0, a2 = 0.0, a3 = 0.0, p = 1.0; /* p = (-1)^n t^(2n) / n! */
+        for (int n = 0; n < 12; ++n) {
+            a1 += p / (2 * n + 1);
+            a2 += 2.0 * p / (2 * n + 3);
+            a3 += 4.0 * p / (3.0 * (2 * n + 5));
+            p *= -t * t / (n + 1);
+        }
+        s[0] = c * t * a1;
+        s[1] = c * t * t * t * a2;
+        s[2] = c * t * t * t * t * t * a3;
+        return;
+    }
+    double e = exp(-t * t);
     s[0] = erf(t);
     s[1] = erf(t) - c * t * e;
     s[2] = erf(t) - c * (t + (2.0 / 3.0) * t * t * t) * e;

@@ -236,3 +236,16 @@ def test_self_convergence_order():
     e1 = np.abs(us[0] - us[1]).max()
     e2 = np.abs(us[1] - us[2]).max()
     assert e1 / e2 > 16
+
+
+def test_smoothing_small_t_series_continuity():
+    # below t = 0.2 the oracle evaluates s_k by their Maclaurin series; the two evaluations of the same
+    # functions must agree across the switch, and s2/t^3, s3/t^5 must keep full relative accuracy at
+    # tiny t (two quadrature points of different families can coincide up to rounding)
+    lo, hi = oracle.smoothing(0.2 - 1e-12), oracle.smoothing(0.2 + 1e-12)
+    np.testing.assert_allclose(lo, hi, rtol=1e-9)
+    t = 1e-16
+    s = oracle.smoothing(t)
+    assert abs(s[0] / t / (2 / SQPI) - 1) < 1e-15
+    assert abs(s[1] / t ** 3 / (4 / (3 * SQPI)) - 1) < 1e-15
+    assert abs(s[2] / t ** 5 / (8 / (15 * SQPI)) - 1) < 1e-15
