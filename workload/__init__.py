@@ -8,10 +8,11 @@ from .surface import (Surface, ellipsoid_quadrature, ellipsoid_normal, ellipsoid
                       closest_point_ellipsoid, ellipsoid_area, sphere_quadrature)
 from .targets import Targets, on_surface_targets, near_targets, grid_targets_outside, concat_targets
 from .density import harmonic_coeffs, harmonic_field
-from .configs import build_config, CONFIGS
+from .configs import build_config, CONFIGS, two_spheres, rigid_motion
 
 __all__ = [
     "Surface", "ellipsoid_quadrature", "ellipsoid_normal", "ellipsoid_project", "closest_point_ellipsoid",
     "ellipsoid_area", "sphere_quadrature", "Targets", "on_surface_targets", "near_targets",
     "grid_targets_outside", "concat_targets", "harmonic_coeffs", "harmonic_field", "build_config", "CONFIGS",
+    "two_spheres", "rigid_motion",
 ]

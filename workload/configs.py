@@ -67,3 +67,19 @@ def build_config(name: str, h: float | None = None, m_near: int | None = None, s
     f0[: surf.n] = f  # on-surface targets: density at x0 is exactly the source value
     return dict(name=name, surf=surf, targets=t, f=f, f0=f0, q=f.copy(), q0=f0.copy(), h=cfg["h"],
                 rho=tuple(cfg["rho"]), axes=cfg["axes"], coeffs=coeffs)
+
+
+def two_spheres(h: float, gap: float, radius: float = 1.0):
+    """Two spheres of the given radius, centres (0,0,0) and (2 radius + gap, 0, 0); each sphere's
+    grid-line quadrature is generated in its own frame (identical point sets).  Returns
+    (centers (2,3), radii (2,), surfaces [s1, s2])."""
+    c1 = (0.0, 0.0, 0.0)
+    c2 = (2.0 * radius + gap, 0.0, 0.0)
+    s1 = ellipsoid_quadrature((radius, radius, radius), h, c1)
+    s2 = ellipsoid_quadrature((radius, radius, radius), h, c2)
+    return np.array([c1, c2]), np.array([radius, radius]), [s1, s2]
+
+
+def rigid_motion(rng: np.random.Generator, nsph: int = 2) -> np.ndarray:
+    """(nsph, 6) translation and rotation per sphere, N(0, 1)."""
+    return rng.standard_normal((nsph, 6))
