@@ -125,6 +125,60 @@ enum { SR_PHASE_FAR = 0, SR_PHASE_NEAR = 1, SR_NPHASES = 2 };
 sr_status sr_set_profiling(sr_ctx *c, int on);
 sr_status sr_get_profile(sr_ctx *c, double *ms, int64_t *evals);
 
+/* ---------------------------------------------------------------------------------------------
+ * Rigid spheres in Stokes flow: the completed double-layer equation for the exterior flow past
+ * rigid spheres (Power & Miranda, SIAM J. Appl. Math. 47 (1987)), with every layer integral
+ * evaluated by sr_eval (double layer; paper eqs. (Stokes_DL2), (extrap_eqn)):
+ *
+ *   (A q)(x) = -1/2 q(x) + sum_m DL_m[q_m](x) + sum_m C_m(x),          x on sphere b,
+ *   C_m(x)   = (1/8 pi) [ S(x - c_m) F_m + L_m x (x - c_m) / |x - c_m|^3 ],
+ *   F_m = sum_p q_p w_p,  L_m = sum_p (x_p - c_m) x q_p w_p   (sums over sphere m),
+ *
+ * where DL_m of a sphere's own points is the on-surface value (chi = 1/2) and of other points the
+ * nearly singular exterior value with q(x0) interpolated on the quadrature grid (cubic, else
+ * quadratic, else linear tensor Lagrange on one coordinate family).  A q = U_b + Omega_b x (x - c_b)
+ * is the rigid-motion problem.  Unknowns and targets: the quadrature points of all spheres, sphere
+ * by sphere, (ntot,3).  The quadrature must be the grid-line quadrature of paper section 2.2 with
+ * the parameters' h, generated in each sphere's frame centred at its centre. */
+typedef struct sr_rigid sr_rigid;
+
+sr_status sr_rigid_create(sr_rigid **out, int device);
+sr_status sr_rigid_destroy(sr_rigid *r);
+/* Parameters of every sphere's evaluator (precision, far method, h, rho, cutoff, treecode). */
+sr_status sr_rigid_set_params(sr_rigid *r, const sr_params *p);
+/* nsph spheres (1..64): centres (nsph,3), radii (nsph) and point counts (nsph) on the HOST; points
+ * x, normals nrm (ntot,3) and weights w (ntot) on the device, concatenated sphere by sphere.
+ * Builds the evaluators, closest points and interpolation stencils; synchronizes `stream`. */
+sr_status sr_rigid_set_spheres(sr_rigid *r, int nsph, const double *centers, const double *radii,
+                               const int64_t *counts, const double *x, const double *nrm, const double *w,
+                               void *stream);
+/* rhs (ntot,3, device) = U_b + Omega_b x (x - c_b); motion (nsph,6) = (U, Omega) per sphere, HOST. */
+sr_status sr_rigid_rhs(sr_rigid *r, const double *motion, double *rhs, void *stream);
+/* out = A q (device arrays (ntot,3)). */
+sr_status sr_rigid_matvec(sr_rigid *r, const double *q, double *out, void *stream);
+/* Solve A x = rhs by restarted GMRES (device arrays).  x_is_guess != 0: x holds the initial guess,
+ * else the iteration starts from 0.  Stops when the relative residual estimate |rhs - A x| / |rhs|
+ * <= tol or after maxit matrix-vector products.  *iters = Arnoldi matrix-vector products;
+ * *relres = the recomputed true relative residual.  SR_ENOCONV if not converged (x holds the last
+ * iterate).  Synchronizes `stream`. */
+sr_status sr_rigid_solve(sr_rigid *r, const double *rhs, double *x, int x_is_guess, double tol, int maxit,
+                         int restart, int *iters, double *relres, void *stream);
+/* Solve A x = rhs by iterative refinement: outer residuals rhs - A x with the operator evaluated in
+ * FP64 (SR_FP64 evaluators, built on the first call), corrections from restarted GMRES with the
+ * parameters' precision, each solved to the relative residual inner_tol (0 < inner_tol < 1).  Use it
+ * with SR_MIXED parameters when tol lies below the mixed operator's own error (about 1e-7 relative).
+ * Stops when the FP64 relative residual <= tol or after maxit inner matrix-vector products.
+ * *iters = inner Arnoldi products, *outer = corrections applied, *relres = the final FP64 relative
+ * residual.  SR_ENOCONV if not converged (x holds the last iterate).  Synchronizes `stream`. */
+sr_status sr_rigid_solve_refined(sr_rigid *r, const double *rhs, double *x, int x_is_guess, double tol,
+                                 double inner_tol, int maxit, int restart, int *iters, int *outer, double *relres,
+                                 void *stream);
+/* Exterior flow u (m,3) at points y (m,3) outside every sphere: sum_m DL_m[q_m] (chi = 0) + C_m.
+ * Synchronizes `stream`. */
+sr_status sr_rigid_velocity(sr_rigid *r, const double *q, int64_t m, const double *y, double *u, void *stream);
+/* Message describing the last sr_rigid_* failure on this thread. */
+const char *sr_rigid_last_error(void);
+
 /* Message describing the last failure on this thread ("" if none). */
 const char *sr_last_error(void);
 

@@ -7,10 +7,12 @@ convenience wrapper.  Nothing here computes the method on the CPU.
 from .binding import (EXPORTS, LIB_PATH, SR_DIRECT, SR_DL, SR_FP64, SR_MIXED, SR_SL, SR_TREE, SrError, SrParams,
                       load_library, sr_create, sr_default_params, sr_destroy, sr_eval, sr_set_density,
                       sr_set_params, sr_set_surface, sr_version, sr_set_profiling, sr_get_profile,
-                      SR_PHASE_FAR, SR_PHASE_NEAR)
-from .evaluator import Evaluator
+                      SR_PHASE_FAR, SR_PHASE_NEAR, sr_rigid_create, sr_rigid_destroy, sr_rigid_set_params,
+                      sr_rigid_set_spheres, sr_rigid_rhs, sr_rigid_matvec, sr_rigid_solve, sr_rigid_velocity)
+from .evaluator import Evaluator, RigidSpheres
 
 __all__ = ["EXPORTS", "LIB_PATH", "SR_DIRECT", "SR_DL", "SR_FP64", "SR_MIXED", "SR_SL", "SR_TREE", "SrError",
            "SrParams", "load_library", "sr_create", "sr_default_params", "sr_destroy", "sr_eval", "sr_set_density",
-           "sr_set_params", "sr_set_surface", "sr_version", "Evaluator", "sr_set_profiling", "sr_get_profile",
-           "SR_PHASE_FAR", "SR_PHASE_NEAR"]
+           "sr_set_params", "sr_set_surface", "sr_version", "Evaluator", "RigidSpheres", "sr_set_profiling", "sr_get_profile",
+           "SR_PHASE_FAR", "SR_PHASE_NEAR", "sr_rigid_create", "sr_rigid_destroy", "sr_rigid_set_params",
+           "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_velocity"]

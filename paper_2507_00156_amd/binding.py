@@ -21,7 +21,9 @@ _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR
 
 # every symbol the header declares; the CPU test-suite checks that the library exports each one
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
-           "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_last_error", "sr_version")
+           "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy",
+           "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
+           "sr_rigid_solve_refined", "sr_rigid_velocity", "sr_rigid_last_error", "sr_last_error", "sr_version")
 SR_PHASE_FAR, SR_PHASE_NEAR, SR_NPHASES = 0, 1, 2
 
 
@@ -59,12 +61,27 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_eval.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.sr_set_profiling.argtypes = [vp, C.c_int]
     L.sr_get_profile.argtypes = [vp, d, C.POINTER(C.c_int64)]
+    L.sr_rigid_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.sr_rigid_destroy.argtypes = [vp]
+    L.sr_rigid_set_params.argtypes = [vp, C.POINTER(SrParams)]
+    L.sr_rigid_set_spheres.argtypes = [vp, C.c_int, d, d, C.POINTER(C.c_int64), vp, vp, vp, vp]
+    L.sr_rigid_rhs.argtypes = [vp, d, vp, vp]
+    L.sr_rigid_matvec.argtypes = [vp, vp, vp, vp]
+    L.sr_rigid_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_double), vp]
+    L.sr_rigid_solve_refined.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
+                                         C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double), vp]
+    L.sr_rigid_velocity.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.sr_rigid_last_error.argtypes = []
+    L.sr_rigid_last_error.restype = C.c_char_p
     L.sr_last_error.argtypes = []
     L.sr_last_error.restype = C.c_char_p
     L.sr_version.argtypes = []
     L.sr_version.restype = C.c_char_p
     for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
-               "sr_set_profiling", "sr_get_profile"):
+               "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy", "sr_rigid_set_params",
+               "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_solve_refined",
+               "sr_rigid_velocity"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L
@@ -157,6 +174,82 @@ def sr_get_profile(ctx):
     ne = C.c_int64()
     _check("sr_get_profile", load_library().sr_get_profile(ctx, ms, C.byref(ne)))
     return list(ms), int(ne.value)
+
+
+def _rcheck(fn: str, st: int) -> None:
+    if st != SR_OK:
+        raise SrError(fn, st, load_library().sr_rigid_last_error().decode())
+
+
+def sr_rigid_create(device: int = 0):
+    h = C.c_void_p()
+    _rcheck("sr_rigid_create", load_library().sr_rigid_create(C.byref(h), int(device)))
+    return h
+
+
+def sr_rigid_destroy(r) -> None:
+    _rcheck("sr_rigid_destroy", load_library().sr_rigid_destroy(r))
+
+
+def sr_rigid_set_params(r, params: SrParams) -> None:
+    _rcheck("sr_rigid_set_params", load_library().sr_rigid_set_params(r, C.byref(params)))
+
+
+def sr_rigid_set_spheres(r, centers, radii, counts, x, nrm, w, stream=None) -> None:
+    import numpy as np
+
+    cen = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+    rad = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+    cnt = np.ascontiguousarray(counts, dtype=np.int64).ravel()
+    ns = cen.shape[0]
+    if rad.size != ns or cnt.size != ns or int(cnt.sum()) != int(x.shape[0]):
+        raise ValueError("sr_rigid_set_spheres: inconsistent sizes")
+    dp = C.POINTER(C.c_double)
+    _rcheck("sr_rigid_set_spheres", load_library().sr_rigid_set_spheres(
+        r, ns, cen.ctypes.data_as(dp), rad.ctypes.data_as(dp), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+        _ptr(x, "x", 3), _ptr(nrm, "nrm", 3), _ptr(w, "w"), _stream(stream)))
+
+
+def sr_rigid_rhs(r, motion, rhs, stream=None) -> None:
+    import numpy as np
+
+    mo = np.ascontiguousarray(motion, dtype=np.float64).reshape(-1, 6)
+    _rcheck("sr_rigid_rhs", load_library().sr_rigid_rhs(r, mo.ctypes.data_as(C.POINTER(C.c_double)),
+                                                        _ptr(rhs, "rhs", 3), _stream(stream)))
+
+
+def sr_rigid_matvec(r, q, out, stream=None) -> None:
+    _rcheck("sr_rigid_matvec", load_library().sr_rigid_matvec(r, _ptr(q, "q", 3), _ptr(out, "out", 3),
+                                                              _stream(stream)))
+
+
+def sr_rigid_solve(r, rhs, x, x_is_guess=False, tol=1e-8, maxit=200, restart=60, stream=None):
+    """Returns (iterations, relative residual)."""
+    it = C.c_int()
+    rr = C.c_double()
+    st = load_library().sr_rigid_solve(r, _ptr(rhs, "rhs", 3), _ptr(x, "x", 3), int(bool(x_is_guess)), float(tol),
+                                       int(maxit), int(restart), C.byref(it), C.byref(rr), _stream(stream))
+    _rcheck("sr_rigid_solve", st)
+    return int(it.value), float(rr.value)
+
+
+def sr_rigid_solve_refined(r, rhs, x, x_is_guess=False, tol=1e-10, inner_tol=1e-4, maxit=400, restart=60,
+                           stream=None):
+    """Returns (inner iterations, outer corrections, FP64 relative residual)."""
+    it = C.c_int()
+    no = C.c_int()
+    rr = C.c_double()
+    st = load_library().sr_rigid_solve_refined(r, _ptr(rhs, "rhs", 3), _ptr(x, "x", 3), int(bool(x_is_guess)),
+                                               float(tol), float(inner_tol), int(maxit), int(restart), C.byref(it),
+                                               C.byref(no), C.byref(rr), _stream(stream))
+    _rcheck("sr_rigid_solve_refined", st)
+    return int(it.value), int(no.value), float(rr.value)
+
+
+def sr_rigid_velocity(r, q, y, u, stream=None) -> None:
+    _rcheck("sr_rigid_velocity", load_library().sr_rigid_velocity(r, _ptr(q, "q", 3), int(y.shape[0]),
+                                                                  _ptr(y, "y", 3), _ptr(u, "u", 3),
+                                                                  _stream(stream)))
 
 
 def sr_version() -> str:

@@ -105,6 +105,7 @@ struct sr_ctx {
 
     CellGrid grid{};
     double grid_rnear = -1.0;
+    double org[3] = {0.0, 0.0, 0.0};  // centre of the points' bounding box: origin of the FP32 coordinates
     bool layout_dirty = true, pack_dirty = true;
 
     // treecode far field
@@ -247,7 +248,7 @@ sr_status ensure_packed(sr_ctx *c, hipStream_t s)
         SR_HIP(c->pos64.reserve(c->n));
         SR_HIP(c->pos32.reserve(c->n));
         SR_HIP(launch_pack(c->x.p, c->nrm.p, c->w.p, c->have_sl ? c->f.p : nullptr, c->have_dl ? c->q.p : nullptr,
-                           c->perm.p, c->n, c->rec64.p, c->rec32.p, c->pos64.p, c->pos32.p, s));
+                           c->perm.p, c->n, c->org, c->rec64.p, c->rec32.p, c->pos64.p, c->pos32.p, s));
         c->pack_dirty = false;
     }
     return SR_OK;
@@ -282,9 +283,9 @@ sr_status ensure_tree(sr_ctx *c, hipStream_t s)
             p64[k].x = T.proxy_xyz[3 * k];
             p64[k].y = T.proxy_xyz[3 * k + 1];
             p64[k].z = T.proxy_xyz[3 * k + 2];
-            p32[k].x = (float)p64[k].x;
-            p32[k].y = (float)p64[k].y;
-            p32[k].z = (float)p64[k].z;
+            p32[k].x = (float)(p64[k].x - c->org[0]);
+            p32[k].y = (float)(p64[k].y - c->org[1]);
+            p32[k].z = (float)(p64[k].z - c->org[2]);
         }
         SR_HIP(hipMemcpyAsync(c->t_nodes.p, T.nodes.data(), nn * sizeof(TreeNode), hipMemcpyHostToDevice, s));
         SR_HIP(hipMemcpyAsync(c->t_item_node.p, T.item_node.data(), ni * sizeof(int), hipMemcpyHostToDevice, s));
@@ -320,7 +321,7 @@ sr_status ensure_tree(sr_ctx *c, hipStream_t s)
     }
     if (c->tree_weights_dirty) {
         SR_HIP(launch_pack(c->x.p, c->nrm.p, c->w.p, c->have_sl ? c->f.p : nullptr, c->have_dl ? c->q.p : nullptr,
-                           c->t_perm.p, c->n, c->t_rec64.p, c->t_rec32.p, nullptr, nullptr, s));
+                           c->t_perm.p, c->n, c->org, c->t_rec64.p, c->t_rec32.p, nullptr, nullptr, s));
         SR_HIP(launch_anterp(c->tdev, c->tree.cosk.data(), c->t_partial.p, s));
         c->tree_weights_dirty = false;
     }
@@ -449,6 +450,14 @@ sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nr
     SR_HIP(hipMemcpyAsync(c->nrm.p, nrm, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
     SR_HIP(hipMemcpyAsync(c->w.p, w, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     c->n = n;
+    for (int d = 0; d < 3; ++d) {
+        double lo = hx[d], hi = hx[d];
+        for (int64_t i = 1; i < n; ++i) {
+            lo = std::min(lo, hx[3 * i + d]);
+            hi = std::max(hi, hx[3 * i + d]);
+        }
+        c->org[d] = 0.5 * (lo + hi);
+    }
     c->hx.swap(hx);
     c->have_surface = true;
     c->have_sl = c->have_dl = false;
@@ -514,6 +523,7 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     a.q0 = q0;
     a.u = u;
     a.v = v;
+    for (int d = 0; d < 3; ++d) a.org[d] = c->prm.precision == SR_MIXED ? c->org[d] : 0.0;
     a.u_delta = u_delta;
     a.v_delta = v_delta;
 

@@ -22,6 +22,11 @@ namespace {
 
 constexpr int kTile = 32;  // FP32 partial-sum length before promotion to FP64
 
+struct Org3 {
+    double v[3];
+    __device__ double operator[](int i) const { return v[i]; }
+};
+
 __device__ __forceinline__ float rsqrt_t(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_t(double v) { return rsqrt(v); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -33,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
                                                             const double *__restrict__ n0,
                                                             const double *__restrict__ f0,
                                                             const double *__restrict__ q0, int m, T rc2,
-                                                            double *__restrict__ part)
+                                                            Org3 org, double *__restrict__ part)
 {
     const int split = blockIdx.x % kFarSplits;
     const int tile = blockIdx.x / kFarSplits;
@@ -48,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
         tix[k] = t;
         const int tt = t < m ? t : m - 1;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) ty[k][i] = (T)y[3 * tt + i];
+        for (int i = 0; i < 3; ++i) ty[k][i] = (T)(y[3 * tt + i] - org[i]);
         tc[k] = 0;
         if (SL) tc[k] = (T)(f0[3 * tt] * n0[3 * tt] + f0[3 * tt + 1] * n0[3 * tt + 1] + f0[3 * tt + 2] * n0[3 * tt + 2]);
 #pragma unroll
@@ -128,7 +133,7 @@ hipError_t launch_t(const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, d
     const int chunk = (int)((n + kFarSplits - 1) / kFarSplits);
     dim3 grid(tiles * kFarSplits), block(kBlock);
     hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0, a.f0,
-                       a.q0, m, rc2, part);
+                       a.q0, m, rc2, Org3{a.org[0], a.org[1], a.org[2]}, part);
     return hipGetLastError();
 }
 

@@ -69,6 +69,10 @@ struct EvalArgs {
     int64_t m;
     const double *y, *x0, *n0, *b, *f0, *q0;
     double *u, *v, *u_delta, *v_delta;
+    // Origin of the single-precision coordinates: the FP32 records hold x - org and the kernels
+    // round y - org, so their rounding error scales with the source set's extent, not with its
+    // distance from (0,0,0).  Zero for the FP64 path.
+    double org[3];
 };
 
 // The three smoothing lengths in ascending order (the extrapolation is symmetric under reordering
@@ -85,7 +89,7 @@ struct DevParams {
 
 // ---- kernel launchers (return hipSuccess or the launch error) ----
 hipError_t launch_pack(const double *x, const double *nrm, const double *w, const double *f, const double *q,
-                       const int64_t *perm, int64_t n, SrcRec<double> *rec64, SrcRec<float> *rec32,
+                       const int64_t *perm, int64_t n, const double org[3], SrcRec<double> *rec64, SrcRec<float> *rec32,
                        Pos4<double> *pos64, Pos4<float> *pos32, hipStream_t s);
 
 hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,

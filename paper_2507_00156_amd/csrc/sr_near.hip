@@ -67,9 +67,33 @@ __device__ __forceinline__ double I2f(double lam)
     return (2.0 / 3.0) * ((0.5 - lam * lam) * exp(-lam * lam) * kInvSqrtPi + a * a * a * erfc(a));
 }
 
-// s1, s2, s3 at t >= 0 (eqs. (s1)-(s3)), replaced by 1 for t > cutoff.  erfc(t) = exp(-t^2) erfcx(t),
-// erfcx from the interpolating polynomial of sr_erfcx_table.h (|erfc error| < 1e-15 on [0, 6.25]);
-// beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
+// Maclaurin coefficients for t < kSeriesT: s1 = c t sum A1_n t^2n, s2 = c t^3 sum A2_n t^2n,
+// s3 = c t^5 sum A3_n t^2n (c = 2/sqrt(pi)), with A1_n = (-1)^n / (n! (2n+1)),
+// A2_n = (-1)^n 2 / (n! (2n+3)), A3_n = (-1)^n 4 / (3 n! (2n+5)) (series of erf and exp).
+constexpr double kSeriesT = 0.2;
+constexpr int kSeriesN = 12;
+struct SeriesCoef {
+    double a1[kSeriesN], a2[kSeriesN], a3[kSeriesN];
+};
+constexpr SeriesCoef make_series()
+{
+    SeriesCoef c{};
+    double f = 1.0;  // (-1)^n / n!
+    for (int n = 0; n < kSeriesN; ++n) {
+        c.a1[n] = f / (2 * n + 1);
+        c.a2[n] = 2.0 * f / (2 * n + 3);
+        c.a3[n] = 4.0 * f / (3.0 * (2 * n + 5));
+        f = -f / (n + 1);
+    }
+    return c;
+}
+__constant__ constexpr SeriesCoef kSeries = make_series();
+
+// s1, s2, s3 at t >= 0 (eqs. (s1)-(s3)), replaced by 1 for t > cutoff and by 0 for t < kSeriesT (the
+// pairs closer than kSeriesT delta are added separately by near_pair_series, whose Maclaurin series
+// keep the relative accuracy of s2 ~ t^3 and s3 ~ t^5 that the differences below would lose).
+// erfc(t) = exp(-t^2) erfcx(t), erfcx from the interpolating polynomial of sr_erfcx_table.h (|erfc
+// error| < 1e-15 on [0, 6.25]); beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
 __device__ __forceinline__ void smoothing3(double t, double cutoff, double &s1, double &s2, double &s3)
 {
     using namespace erfcx_poly;
@@ -89,9 +113,27 @@ __device__ __forceinline__ void smoothing3(double t, double cutoff, double &s1, 
     const double P2 = __builtin_fma(kTwoOverSqrtPi, t, R);
     const double P3 = __builtin_fma((2.0 / 3.0) * kTwoOverSqrtPi * t * t, t, P2);
     const double Ec = t > cutoff ? 0.0 : E;  // beyond the cut-off s1 = s2 = s3 = 1 exactly
-    s1 = __builtin_fma(-Ec, R, 1.0);
-    s2 = __builtin_fma(-Ec, P2, 1.0);
-    s3 = __builtin_fma(-Ec, P3, 1.0);
+    const bool ser = t < kSeriesT;
+    s1 = ser ? 0.0 : __builtin_fma(-Ec, R, 1.0);
+    s2 = ser ? 0.0 : __builtin_fma(-Ec, P2, 1.0);
+    s3 = ser ? 0.0 : __builtin_fma(-Ec, P3, 1.0);
+}
+
+// s1, s2, s3 for t < kSeriesT from their Maclaurin series.
+__device__ __forceinline__ void series3(double t, double &s1, double &s2, double &s3)
+{
+    const double t2 = t * t;
+    double b1 = kSeries.a1[kSeriesN - 1], b2 = kSeries.a2[kSeriesN - 1], b3 = kSeries.a3[kSeriesN - 1];
+#pragma unroll 1
+    for (int n = kSeriesN - 2; n >= 0; --n) {
+        b1 = __builtin_fma(b1, t2, kSeries.a1[n]);
+        b2 = __builtin_fma(b2, t2, kSeries.a2[n]);
+        b3 = __builtin_fma(b3, t2, kSeries.a3[n]);
+    }
+    const double ct = kTwoOverSqrtPi * t;
+    s1 = ct * b1;
+    s2 = ct * t2 * b2;
+    s3 = ct * t2 * t2 * b3;
 }
 
 __device__ __forceinline__ double pick3(const double (&v)[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
@@ -104,15 +146,13 @@ struct Acc {
     double sl[3][3], dl[3][3];
 };
 
-// Adds one pair's contribution at the smoothing length of sorted position J.
+// Adds one pair's contribution with smoothing factors s1, s2, s3 at sorted position J.
 template <int J, bool SL, bool DL>
-__device__ __forceinline__ void accumulate_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
-                                                 double dz, double gx, double gy, double gz, double dg, double t1x,
-                                                 double t1y, double t1z, double ex, double ey, double ez,
-                                                 const DevParams &p, Acc &A)
+__device__ __forceinline__ void add_delta(double s1, double s2, double s3, double ir, double ir3, double ir5,
+                                          double dx, double dy, double dz, double gx, double gy, double gz,
+                                          double dg, double t1x, double t1y, double t1z, double ex, double ey,
+                                          double ez, Acc &A)
 {
-    double s1, s2, s3;
-    smoothing3(r * p.inv_delta[J], p.cutoff, s1, s2, s3);
     if (SL) {
         const double k1 = s1 * ir, k2 = dg * s2 * ir3;
         A.sl[J][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[J][0]));
@@ -127,13 +167,43 @@ __device__ __forceinline__ void accumulate_delta(double r, double ir, double ir3
     }
 }
 
-// One near pair, accumulated at the three smoothing lengths (sorted-delta order).
-template <bool SL, bool DL>
-__device__ __forceinline__ void near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
+template <int J, bool SL, bool DL>
+__device__ __forceinline__ void accumulate_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
+                                                 double dz, double gx, double gy, double gz, double dg, double t1x,
+                                                 double t1y, double t1z, double ex, double ey, double ez,
+                                                 const DevParams &p, Acc &A)
+{
+    double s1, s2, s3;
+    smoothing3(r * p.inv_delta[J], p.cutoff, s1, s2, s3);
+    add_delta<J, SL, DL>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, A);
+}
+
+// The contributions that smoothing3 left out (t < kSeriesT), from the series.  Rarely executed: only
+// pairs closer than kSeriesT times the largest delta reach it.
+template <int J, bool SL, bool DL>
+__device__ __forceinline__ void series_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
+                                             double dz, double gx, double gy, double gz, double dg, double t1x,
+                                             double t1y, double t1z, double ex, double ey, double ez,
+                                             const DevParams &p, Acc &A)
+{
+    const double t = r * p.inv_delta[J];
+    if (t < kSeriesT) {
+        double s1, s2, s3;
+        series3(t, s1, s2, s3);
+        add_delta<J, SL, DL>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, A);
+    }
+}
+
+// One near pair, accumulated at the three smoothing lengths (sorted-delta order).  SER = false: the
+// closed-form smoothing factors, leaving out t < kSeriesT; returns whether some t is below kSeriesT
+// (then the caller calls it again with SER = true, which adds just those terms from the series).
+template <bool SL, bool DL, bool SER>
+__device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
 {
     const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 == 0.0) {
+        if (SER) return false;
         // target on a quadrature point: limit of s1(r/delta)/r is 2/(sqrt(pi) delta); the d d s2/r^3
         // term and the whole double-layer term vanish
         if (SL) {
@@ -146,7 +216,7 @@ __device__ __forceinline__ void near_pair(const SrcRec<double> &s, const Target 
                 A.sl[j][2] += gz * l;
             }
         }
-        return;
+        return false;
     }
     const double ir = rsqrt(r2);
     const double r = r2 * ir;
@@ -184,9 +254,29 @@ __device__ __forceinline__ void near_pair(const SrcRec<double> &s, const Target 
         ey = hy * c2h + ny * c2n - rmb * t1y;
         ez = hz * c2h + nz * c2n - rmb * t1z;
     }
+    if (SER) {
+        series_delta<0, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+        series_delta<1, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+        series_delta<2, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+        return false;
+    }
     accumulate_delta<0, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
     accumulate_delta<1, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
     accumulate_delta<2, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+    return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
+}
+
+// A near pair: the closed-form pass, then (rarely) the series pass.  The empty asm hides that the
+// second load reads the same record, so the record is not kept in registers across the first pass.
+template <bool SL, bool DL>
+__device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
+                                               const DevParams &p, Acc &A)
+{
+    if (near_pair<SL, DL, false>(rec64[k], T, p, A)) {
+        int kk = k;
+        asm volatile("" : "+v"(kk));
+        near_pair<SL, DL, true>(rec64[kk], T, p, A);
+    }
 }
 
 template <typename TC, bool SL, bool DL>
@@ -215,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
     }
     T.b = a.b[t];
     T.c = SL ? a.f0[3 * t] * T.n[0] + a.f0[3 * t + 1] * T.n[1] + a.f0[3 * t + 2] * T.n[2] : 0.0;
-    const TC tyx = (TC)T.y[0], tyy = (TC)T.y[1], tyz = (TC)T.y[2];
+    const TC tyx = (TC)(T.y[0] - a.org[0]), tyy = (TC)(T.y[1] - a.org[1]), tyz = (TC)(T.y[2] - a.org[2]);
 
     int ci[3];
 #pragma unroll
@@ -259,13 +349,13 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
                     if (lane + kWave < cnt) queue[lane] = queue[lane + kWave];
                     cnt -= kWave;
                     wave_lds_sync();
-                    near_pair<SL, DL>(rec64[k2], T, p, A);
+                    near_pair_full<SL, DL>(rec64, k2, T, p, A);
                 }
             }
         }
     }
     wave_lds_sync();
-    if (lane < cnt) near_pair<SL, DL>(rec64[queue[lane]], T, p, A);
+    if (lane < cnt) near_pair_full<SL, DL>(rec64, queue[lane], T, p, A);
 
 #pragma unroll
     for (int j = 0; j < 3; ++j)

@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         yd[i] = a.y[3 * t + i];
-        L.y[i] = (T)yd[i];
+        L.y[i] = (T)(yd[i] - a.org[i]);
         L.q0[i] = DL ? (T)a.q0[3 * t + i] : (T)0;
     }
     L.c = SL ? (T)(a.f0[3 * t] * a.n0[3 * t] + a.f0[3 * t + 1] * a.n0[3 * t + 1] + a.f0[3 * t + 2] * a.n0[3 * t + 2])
