@@ -5,7 +5,7 @@ spheres) to the density at the coarse quadrature points.  The density solves a l
 whose right-hand side is linear in m, so the network is made exactly linear in m: four layers of
 width 256 act on the gap alone, and the fourth is a 256 x 12 matrix C(g) contracted with m.
 
-    gt = (g - g_mid) / g_half
+    gt = (ln g - g_mid) / g_half          (near contact the flow varies like log(gap))
     h1 = tanh(W1 gt + b1)                 W1 (W,1)
     h2 = tanh(W2 h1 + b2)                 W2 (W,W)
     h3 = tanh(W3 h2 + b3)                 W3 (W,W)
@@ -33,7 +33,7 @@ def shapes(width: int, nout: int):
 
 def forward(p, g, m, g_mid, g_half):
     """p: dict of parameters; g (B,), m (B,12).  Returns (o (B,P), cache)."""
-    gt = ((np.asarray(g, float) - g_mid) / g_half)[:, None]
+    gt = ((np.log(np.asarray(g, float)) - g_mid) / g_half)[:, None]
     h1 = np.tanh(gt @ p["W1"].T + p["b1"])
     h2 = np.tanh(h1 @ p["W2"].T + p["b2"])
     h3 = np.tanh(h2 @ p["W3"].T + p["b3"])

@@ -11,6 +11,8 @@ import numpy as np
 import pytest
 
 import workload
+
+GMID, GHALF = np.log(0.02 * 0.2) / 2, np.log(0.2 / 0.02) / 2  # ln g over [0.02, 0.2] -> [-1, 1]
 from oracle import mlp
 
 
@@ -26,7 +28,7 @@ def tiny(width=6, nout=5, seed=1):
 @pytest.mark.parametrize("name", mlp.NAMES)
 def test_gradient_matches_finite_differences(name):
     p, g, m, t = tiny()
-    o, cache = mlp.forward(p, g, m, 0.11, 0.09)
+    o, cache = mlp.forward(p, g, m, GMID, GHALF)
     gr = mlp.backward(p, cache, o, t)
     rng = np.random.default_rng(5)
     flat = p[name].reshape(-1)
@@ -35,9 +37,9 @@ def test_gradient_matches_finite_differences(name):
     for i in idx:
         old = flat[i]
         flat[i] = old + eps
-        lp = mlp.loss(mlp.forward(p, g, m, 0.11, 0.09)[0], t)
+        lp = mlp.loss(mlp.forward(p, g, m, GMID, GHALF)[0], t)
         flat[i] = old - eps
-        lm = mlp.loss(mlp.forward(p, g, m, 0.11, 0.09)[0], t)
+        lm = mlp.loss(mlp.forward(p, g, m, GMID, GHALF)[0], t)
         flat[i] = old
         fd = (lp - lm) / (2 * eps)
         an = gr[name].reshape(-1)[i]
@@ -49,11 +51,11 @@ def test_output_is_linear_in_motion():
     rng = np.random.default_rng(9)
     m2 = rng.standard_normal(m.shape)
     a, b = 0.7, -1.9
-    o1 = mlp.forward(p, g, m, 0.11, 0.09)[0]
-    o2 = mlp.forward(p, g, m2, 0.11, 0.09)[0]
-    o3 = mlp.forward(p, g, a * m + b * m2, 0.11, 0.09)[0]
+    o1 = mlp.forward(p, g, m, GMID, GHALF)[0]
+    o2 = mlp.forward(p, g, m2, GMID, GHALF)[0]
+    o3 = mlp.forward(p, g, a * m + b * m2, GMID, GHALF)[0]
     np.testing.assert_allclose(o3, a * o1 + b * o2, rtol=1e-12, atol=1e-12)
-    assert np.abs(mlp.forward(p, g, 0 * m, 0.11, 0.09)[0]).max() == 0.0
+    assert np.abs(mlp.forward(p, g, 0 * m, GMID, GHALF)[0]).max() == 0.0
 
 
 def test_adam_constant_gradient_closed_form():
@@ -73,5 +75,5 @@ def test_adam_constant_gradient_closed_form():
 def test_zero_head_loss():
     p, g, m, t = tiny()
     p["Wh"][:] = 0.0
-    o = mlp.forward(p, g, m, 0.11, 0.09)[0]
+    o = mlp.forward(p, g, m, GMID, GHALF)[0]
     assert mlp.loss(o, t) == pytest.approx(np.mean(t ** 2), rel=1e-15)
