@@ -165,8 +165,12 @@ sr_status sr_rigid_solve(sr_rigid *r, const double *rhs, double *x, int x_is_gue
                          int restart, int *iters, double *relres, void *stream);
 /* Solve A x = rhs by iterative refinement: outer residuals rhs - A x with the operator evaluated in
  * FP64 (SR_FP64 evaluators, built on the first call), corrections from restarted GMRES with the
- * parameters' precision, each solved to the relative residual inner_tol (0 < inner_tol < 1).  Use it
+ * parameters' precision, each reducing the residual by the factor max(inner_tol, tol |rhs| / (2 |r|))
+ * (at most 0.5; 0 < inner_tol < 1, about 1e-6 suits SR_MIXED), so a pass stops once the outer
+ * tolerance is within reach.  Use it
  * with SR_MIXED parameters when tol lies below the mixed operator's own error (about 1e-7 relative).
+ * x_is_guess != 0: x holds the initial guess; a guess whose FP64 residual is not below |rhs| (or
+ * is not finite) is replaced by zero.
  * Stops when the FP64 relative residual <= tol or after maxit inner matrix-vector products.
  * *iters = inner Arnoldi products, *outer = corrections applied, *relres = the final FP64 relative
  * residual.  SR_ENOCONV if not converged (x holds the last iterate).  Synchronizes `stream`. */
@@ -176,8 +180,75 @@ sr_status sr_rigid_solve_refined(sr_rigid *r, const double *rhs, double *x, int 
 /* Exterior flow u (m,3) at points y (m,3) outside every sphere: sum_m DL_m[q_m] (chi = 0) + C_m.
  * Synchronizes `stream`. */
 sr_status sr_rigid_velocity(sr_rigid *r, const double *q, int64_t m, const double *y, double *u, void *stream);
-/* Message describing the last sr_rigid_* failure on this thread. */
+/* Message describing the last sr_rigid_* or sr_prolong_* failure on this thread. */
 const char *sr_rigid_last_error(void);
+
+/* Coarse-to-fine interpolation of densities on spheres (the warm start computes the density on a
+ * coarse quadrature and the solve needs it on a fine one).  Each fine point's value is the tensor
+ * Lagrange interpolant on the coarse grid of one coordinate family (cubic, else quadratic, else
+ * linear; the family with the largest |n_i| whose stencil exists), as for q(x0) above.
+ * centers (nsph,3), radii, counts_c, counts_f on the HOST; xc, nc (coarse points and normals,
+ * NC = sum counts_c) and xf (fine points, NF = sum counts_f) on the device, sphere by sphere, each
+ * sphere's coarse set being the grid-line quadrature with spacing hc in its own frame.  Synchronizes
+ * `stream`.  sr_prolong_apply: qf (NF,3) = interpolation of qc (NC,3), device arrays. */
+typedef struct sr_prolong sr_prolong;
+sr_status sr_prolong_create(sr_prolong **out, int device, int nsph, const double *centers, const double *radii,
+                            double hc, const int64_t *counts_c, const double *xc, const double *nc,
+                            const int64_t *counts_f, const double *xf, void *stream);
+sr_status sr_prolong_apply(sr_prolong *p, const double *qc, double *qf, void *stream);
+sr_status sr_prolong_destroy(sr_prolong *p);
+
+/* ---------------------------------------------------------------------------------------------
+ * Warm-start network for the rigid-sphere solve: gap g and the 12 motion parameters m (U, Omega of
+ * sphere 1, then of sphere 2) -> the density at nout coarse unknowns (3 per coarse point).  The
+ * density is linear in m, so the network is too:
+ *   gt = (ln g - g_mid) / g_half;  h1 = tanh(W1 gt + b1);  h2 = tanh(W2 h1 + b2);  h3 = tanh(W3 h2 + b3)
+ *   a4 = W4 h3 + b4 (12 width);  z_w = sum_k a4[12 w + k] m_k;  o = Wh z;  q = s o (s per output)
+ * Matrix products run on BF16 matrix cores with FP32 accumulation; each FP32 operand is split into
+ * BF16 hi + lo and `passes` = 3 (default) sums hi*hi + hi*lo + lo*hi, passes = 1 uses hi*hi only.
+ * Training: loss = mean over batch and outputs of (o - y/s)^2; Adam (beta 0.9, 0.999, eps 1e-8)
+ * on FP32 master weights.
+ * Parameters: one FP32 vector, blocks in the order W1 (width,1), b1, W2 (width,width), b2, W3, b3,
+ * W4 (12 width, width), b4 (12 width), Wh (nout, width), matrices row-major (row = output unit);
+ * sr_mlp_num_params gives its length.  Arrays are device pointers unless noted; gap (batch),
+ * motion (batch,12) and y (batch,nout) are FP64.  In the training calls gap, motion and y hold nrows
+ * rows and idx (batch, int64, device) selects the batch's rows (NULL: rows 0..batch-1), so a data
+ * set can stay resident; indices outside [0, nrows) are rejected (SR_EINVAL).  Calls on one network
+ * must not overlap. */
+typedef struct sr_mlp sr_mlp;
+int64_t sr_mlp_num_params(int width, int64_t nout);
+/* width: multiple of 32 in 32..4096; max_batch 1..4096. */
+sr_status sr_mlp_create(sr_mlp **out, int device, int width, int64_t nout, int max_batch);
+sr_status sr_mlp_destroy(sr_mlp *net);
+/* passes 1 or 3; input normalization g_mid, g_half > 0 of ln g (defaults: ln 0.02 .. ln 0.2 -> -1 .. 1,
+ * g_mid = -2.7607, g_half = 1.1513).  The gap must be > 0. */
+sr_status sr_mlp_set_options(sr_mlp *net, int passes, double g_mid, double g_half);
+/* HOST parameter vector in, out.  Setting resets the Adam moments and step count, and the output
+ * scale to 1 if none was set.  Synchronous. */
+sr_status sr_mlp_set_params(sr_mlp *net, const float *params);
+sr_status sr_mlp_get_params(sr_mlp *net, float *params);
+/* Output scale s (nout, FP64 device): set it, fit it as the root mean square of each output over n
+ * samples y (n,nout), or read it. */
+sr_status sr_mlp_set_output_scale(sr_mlp *net, const double *s, void *stream);
+sr_status sr_mlp_fit_output_scale(sr_mlp *net, int64_t n, const double *y, void *stream);
+sr_status sr_mlp_get_output_scale(sr_mlp *net, double *s, void *stream);
+/* o (batch,nout) FP32, standardized outputs. */
+sr_status sr_mlp_forward(sr_mlp *net, int batch, const double *gap, const double *motion, float *out, void *stream);
+/* q (batch,nout) FP64 = s o: the predicted density. */
+sr_status sr_mlp_predict(sr_mlp *net, int batch, const double *gap, const double *motion, double *q, void *stream);
+/* Gradient of the loss (FP32 device vector of sr_mlp_num_params) without an update; *loss (HOST,
+ * may be NULL; if given the call synchronizes `stream`). */
+sr_status sr_mlp_gradients(sr_mlp *net, int batch, const int64_t *idx, int64_t nrows, const double *gap,
+                           const double *motion, const double *y, float *grad, double *loss, void *stream);
+/* One Adam step with learning rate lr on the batch; *loss as above (the loss before the step). */
+sr_status sr_mlp_train_step(sr_mlp *net, int batch, const int64_t *idx, int64_t nrows, const double *gap,
+                            const double *motion, const double *y, float lr, double *loss, void *stream);
+/* The matrix-product kernel alone, for testing: C (m,n) = A (m,k) B^T with B (n,k), FP32 row-major
+ * device arrays, through BF16 hi/lo operands and `passes` products.  Synchronizes `stream`. */
+sr_status sr_mlp_gemm_test(int device, int passes, int m, int n, int k, const float *a, const float *b, float *c,
+                           void *stream);
+/* Message describing the last sr_mlp_* failure on this thread. */
+const char *sr_mlp_last_error(void);
 
 /* Message describing the last failure on this thread ("" if none). */
 const char *sr_last_error(void);

@@ -23,7 +23,12 @@ _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
            "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy",
            "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
-           "sr_rigid_solve_refined", "sr_rigid_velocity", "sr_rigid_last_error", "sr_last_error", "sr_version")
+           "sr_rigid_solve_refined", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
+           "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
+           "sr_mlp_set_options", "sr_mlp_set_params", "sr_mlp_get_params", "sr_mlp_set_output_scale",
+           "sr_mlp_fit_output_scale", "sr_mlp_get_output_scale", "sr_mlp_forward", "sr_mlp_predict",
+           "sr_mlp_gradients", "sr_mlp_train_step", "sr_mlp_gemm_test", "sr_mlp_last_error", "sr_last_error",
+           "sr_version")
 SR_PHASE_FAR, SR_PHASE_NEAR, SR_NPHASES = 0, 1, 2
 
 
@@ -74,6 +79,32 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_rigid_velocity.argtypes = [vp, vp, i64, vp, vp, vp]
     L.sr_rigid_last_error.argtypes = []
     L.sr_rigid_last_error.restype = C.c_char_p
+    L.sr_prolong_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, d, d, C.c_double, C.POINTER(C.c_int64), vp, vp,
+                                    C.POINTER(C.c_int64), vp, vp]
+    L.sr_prolong_apply.argtypes = [vp, vp, vp, vp]
+    L.sr_prolong_destroy.argtypes = [vp]
+    L.sr_mlp_num_params.argtypes = [C.c_int, i64]
+    L.sr_mlp_num_params.restype = i64
+    L.sr_mlp_create.argtypes = [C.POINTER(vp), C.c_int, C.c_int, i64, C.c_int]
+    L.sr_mlp_destroy.argtypes = [vp]
+    L.sr_mlp_set_options.argtypes = [vp, C.c_int, C.c_double, C.c_double]
+    L.sr_mlp_set_params.argtypes = [vp, C.POINTER(C.c_float)]
+    L.sr_mlp_get_params.argtypes = [vp, C.POINTER(C.c_float)]
+    L.sr_mlp_set_output_scale.argtypes = [vp, vp, vp]
+    L.sr_mlp_fit_output_scale.argtypes = [vp, i64, vp, vp]
+    L.sr_mlp_get_output_scale.argtypes = [vp, vp, vp]
+    L.sr_mlp_forward.argtypes = [vp, C.c_int, vp, vp, vp, vp]
+    L.sr_mlp_predict.argtypes = [vp, C.c_int, vp, vp, vp, vp]
+    L.sr_mlp_gradients.argtypes = [vp, C.c_int, vp, i64, vp, vp, vp, vp, d, vp]
+    L.sr_mlp_train_step.argtypes = [vp, C.c_int, vp, i64, vp, vp, vp, C.c_float, d, vp]
+    L.sr_mlp_gemm_test.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp]
+    L.sr_mlp_last_error.argtypes = []
+    L.sr_mlp_last_error.restype = C.c_char_p
+    for fn in ("sr_prolong_create", "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_create", "sr_mlp_destroy",
+               "sr_mlp_set_options", "sr_mlp_set_params", "sr_mlp_get_params", "sr_mlp_set_output_scale",
+               "sr_mlp_fit_output_scale", "sr_mlp_get_output_scale", "sr_mlp_forward", "sr_mlp_predict",
+               "sr_mlp_gradients", "sr_mlp_train_step", "sr_mlp_gemm_test"):
+        getattr(L, fn).restype = C.c_int
     L.sr_last_error.argtypes = []
     L.sr_last_error.restype = C.c_char_p
     L.sr_version.argtypes = []
@@ -233,7 +264,7 @@ def sr_rigid_solve(r, rhs, x, x_is_guess=False, tol=1e-8, maxit=200, restart=60,
     return int(it.value), float(rr.value)
 
 
-def sr_rigid_solve_refined(r, rhs, x, x_is_guess=False, tol=1e-10, inner_tol=1e-4, maxit=400, restart=60,
+def sr_rigid_solve_refined(r, rhs, x, x_is_guess=False, tol=1e-10, inner_tol=1e-6, maxit=400, restart=60,
                            stream=None):
     """Returns (inner iterations, outer corrections, FP64 relative residual)."""
     it = C.c_int()
@@ -250,6 +281,154 @@ def sr_rigid_velocity(r, q, y, u, stream=None) -> None:
     _rcheck("sr_rigid_velocity", load_library().sr_rigid_velocity(r, _ptr(q, "q", 3), int(y.shape[0]),
                                                                   _ptr(y, "y", 3), _ptr(u, "u", 3),
                                                                   _stream(stream)))
+
+
+def sr_prolong_create(centers, radii, hc, counts_c, xc, nc, counts_f, xf, device: int = 0, stream=None):
+    import numpy as np
+
+    ce = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+    ra = np.ascontiguousarray(radii, dtype=np.float64).ravel()
+    cc = np.ascontiguousarray(counts_c, dtype=np.int64).ravel()
+    cf = np.ascontiguousarray(counts_f, dtype=np.int64).ravel()
+    ns = ce.shape[0]
+    if ra.size != ns or cc.size != ns or cf.size != ns:
+        raise ValueError("sr_prolong_create: inconsistent sphere counts")
+    if xc.shape[0] != int(cc.sum()) or nc.shape[0] != xc.shape[0] or xf.shape[0] != int(cf.sum()):
+        raise ValueError("sr_prolong_create: inconsistent point counts")
+    h = C.c_void_p()
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int64)
+    _rcheck("sr_prolong_create", load_library().sr_prolong_create(
+        C.byref(h), int(device), ns, ce.ctypes.data_as(dp), ra.ctypes.data_as(dp), float(hc), cc.ctypes.data_as(ip),
+        _ptr(xc, "xc", 3), _ptr(nc, "nc", 3), cf.ctypes.data_as(ip), _ptr(xf, "xf", 3), _stream(stream)))
+    return h
+
+
+def sr_prolong_apply(p, qc, qf, stream=None) -> None:
+    _rcheck("sr_prolong_apply", load_library().sr_prolong_apply(p, _ptr(qc, "qc", 3), _ptr(qf, "qf", 3),
+                                                                _stream(stream)))
+
+
+def sr_prolong_destroy(p) -> None:
+    _rcheck("sr_prolong_destroy", load_library().sr_prolong_destroy(p))
+
+
+def _mcheck(fn: str, st: int) -> None:
+    if st != SR_OK:
+        raise SrError(fn, st, load_library().sr_mlp_last_error().decode())
+
+
+def _tptr(t, name: str, dtype_name: str, numel=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+
+    dt = {"f32": torch.float32, "f64": torch.float64, "i64": torch.int64}[dtype_name]
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous CUDA {dt} tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _rows(gap, motion, y) -> int:
+    """Rows of a resident data set (gap (n,), motion (n,12), y (n,nout)), checked for agreement."""
+    n = int(gap.shape[0])
+    if motion.numel() != 12 * n or y.shape[0] != n:
+        raise ValueError("gap, motion and y must have the same number of rows")
+    return n
+
+
+def sr_mlp_num_params(width: int, nout: int) -> int:
+    return int(load_library().sr_mlp_num_params(int(width), int(nout)))
+
+
+def sr_mlp_create(width: int, nout: int, max_batch: int, device: int = 0):
+    h = C.c_void_p()
+    _mcheck("sr_mlp_create", load_library().sr_mlp_create(C.byref(h), int(device), int(width), int(nout),
+                                                          int(max_batch)))
+    return h
+
+
+def sr_mlp_destroy(net) -> None:
+    _mcheck("sr_mlp_destroy", load_library().sr_mlp_destroy(net))
+
+
+def sr_mlp_set_options(net, passes: int = 3, g_mid: float = -2.760730458931123, g_half: float = 1.151292546497023) -> None:
+    _mcheck("sr_mlp_set_options", load_library().sr_mlp_set_options(net, int(passes), float(g_mid), float(g_half)))
+
+
+def sr_mlp_set_params(net, params) -> None:
+    import numpy as np
+
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _mcheck("sr_mlp_set_params", load_library().sr_mlp_set_params(net, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+
+def sr_mlp_get_params(net, nparam: int):
+    import numpy as np
+
+    a = np.empty(int(nparam), dtype=np.float32)
+    _mcheck("sr_mlp_get_params", load_library().sr_mlp_get_params(net, a.ctypes.data_as(C.POINTER(C.c_float))))
+    return a
+
+
+def sr_mlp_set_output_scale(net, s, stream=None) -> None:
+    _mcheck("sr_mlp_set_output_scale", load_library().sr_mlp_set_output_scale(net, _tptr(s, "s", "f64"),
+                                                                              _stream(stream)))
+
+
+def sr_mlp_fit_output_scale(net, y, stream=None) -> None:
+    _mcheck("sr_mlp_fit_output_scale", load_library().sr_mlp_fit_output_scale(net, int(y.shape[0]),
+                                                                              _tptr(y, "y", "f64"), _stream(stream)))
+
+
+def sr_mlp_get_output_scale(net, s, stream=None) -> None:
+    _mcheck("sr_mlp_get_output_scale", load_library().sr_mlp_get_output_scale(net, _tptr(s, "s", "f64"),
+                                                                              _stream(stream)))
+
+
+def sr_mlp_forward(net, gap, motion, out, stream=None) -> None:
+    b = int(gap.shape[0])
+    _mcheck("sr_mlp_forward", load_library().sr_mlp_forward(net, b, _tptr(gap, "gap", "f64"),
+                                                            _tptr(motion, "motion", "f64", 12 * b),
+                                                            _tptr(out, "out", "f32"), _stream(stream)))
+
+
+def sr_mlp_predict(net, gap, motion, q, stream=None) -> None:
+    b = int(gap.shape[0])
+    _mcheck("sr_mlp_predict", load_library().sr_mlp_predict(net, b, _tptr(gap, "gap", "f64"),
+                                                            _tptr(motion, "motion", "f64", 12 * b),
+                                                            _tptr(q, "q", "f64"), _stream(stream)))
+
+
+def sr_mlp_gradients(net, batch, idx, gap, motion, y, grad, stream=None) -> float:
+    loss = C.c_double()
+    _mcheck("sr_mlp_gradients", load_library().sr_mlp_gradients(
+        net, int(batch), _tptr(idx, "idx", "i64"), _rows(gap, motion, y), _tptr(gap, "gap", "f64"),
+        _tptr(motion, "motion", "f64"),
+        _tptr(y, "y", "f64"), _tptr(grad, "grad", "f32"), C.byref(loss), _stream(stream)))
+    return float(loss.value)
+
+
+def sr_mlp_train_step(net, batch, idx, gap, motion, y, lr, want_loss=True, stream=None):
+    loss = C.c_double()
+    _mcheck("sr_mlp_train_step", load_library().sr_mlp_train_step(
+        net, int(batch), _tptr(idx, "idx", "i64"), _rows(gap, motion, y), _tptr(gap, "gap", "f64"),
+        _tptr(motion, "motion", "f64"),
+        _tptr(y, "y", "f64"), float(lr), C.byref(loss) if want_loss else None, _stream(stream)))
+    return float(loss.value) if want_loss else None
+
+
+def sr_mlp_gemm_test(a, b, c, passes: int = 3, device: int = 0, stream=None) -> None:
+    m, k = a.shape
+    n = b.shape[0]
+    if b.shape[1] != k or tuple(c.shape) != (m, n):
+        raise ValueError("sr_mlp_gemm_test: shapes")
+    _mcheck("sr_mlp_gemm_test", load_library().sr_mlp_gemm_test(int(device), int(passes), int(m), int(n), int(k),
+                                                                _tptr(a, "a", "f32"), _tptr(b, "b", "f32"),
+                                                                _tptr(c, "c", "f32"), _stream(stream)))
 
 
 def sr_version() -> str:

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -860,6 +861,7 @@ sr_status sr_rigid_solve_refined(sr_rigid *R, const double *rhs, double *x, int 
         hipLaunchKernelGGL(zero_kernel, dim3(nblocks(n)), dim3(256), 0, s, x, n);
         RHIP(hipGetLastError());
     }
+    bool first = true;
     while (!conv) {
         // outer residual with the FP64 operator
         RSR(rigid_matvec(R, R->ctx64, x, R->rr.p, s));
@@ -868,16 +870,26 @@ sr_status sr_rigid_solve_refined(sr_rigid *R, const double *rhs, double *x, int 
         double r2 = 0.0;
         RSR(mdot(R, R->rr.p, n, 1, R->rr.p, n, &r2, s));
         rel = std::sqrt(r2) / bn;
+        if (first && x_is_guess && !(rel < 1.0)) {
+            // a guess no better than zero (or not finite): start from zero instead
+            hipLaunchKernelGGL(zero_kernel, dim3(nblocks(n)), dim3(256), 0, s, x, n);
+            RHIP(hipGetLastError());
+            first = false;
+            continue;
+        }
+        first = false;
         if (rel <= tol) {
             conv = true;
             break;
         }
         if (total >= maxit) break;
-        // correction from the working-precision operator, solved to inner_tol relative to the residual
+        // correction from the working-precision operator: reduce the residual by inner_tol, or only
+        // as far as the outer tolerance needs (with a factor 2 of margin), whichever is less work
+        const double eta = std::min(0.5, std::max(inner_tol, 0.5 * tol / rel));
         int it = 0;
         double irel = 0.0;
         bool iconv = false;
-        RSR(gmres_solve(R, R->ctx, R->rr.p, R->dd.p, false, inner_tol, maxit - total, restart, &it, &irel, &iconv, s));
+        RSR(gmres_solve(R, R->ctx, R->rr.p, R->dd.p, false, eta, maxit - total, restart, &it, &irel, &iconv, s));
         total += it;
         ++nout;
         hipLaunchKernelGGL(axpby_kernel, dim3(nblocks(n)), dim3(256), 0, s, 1.0, R->dd.p, 1.0, x, n);
@@ -891,6 +903,104 @@ sr_status sr_rigid_solve_refined(sr_rigid *R, const double *rhs, double *x, int 
     return SR_OK;
 }
 
+
+// ---- coarse-to-fine interpolation of densities on spheres ----
+
+struct sr_prolong {
+    int device = 0;
+    int nsph = 0;
+    std::vector<int64_t> offc, offf;
+    std::vector<Buf<int>> idx;
+    std::vector<Buf<double>> wts;
+};
+
+sr_status sr_prolong_create(sr_prolong **out, int device, int nsph, const double *centers, const double *radii,
+                            double hc, const int64_t *counts_c, const double *xc, const double *nc,
+                            const int64_t *counts_f, const double *xf, void *stream)
+{
+    g_rerr.clear();
+    if (!out || !centers || !radii || !counts_c || !xc || !nc || !counts_f || !xf)
+        return rfail(SR_EINVAL, "sr_prolong_create: NULL argument");
+    *out = nullptr;
+    if (nsph < 1 || nsph > 64) return rfail(SR_EINVAL, "sr_prolong_create: nsph must be in 1..64");
+    if (!(hc > 0.0)) return rfail(SR_EINVAL, "sr_prolong_create: hc must be > 0");
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(device) != hipSuccess) return rfail(SR_ENODEV, "sr_prolong_create: cannot select device");
+    struct Restore {
+        int d;
+        ~Restore()
+        {
+            if (d >= 0) (void)hipSetDevice(d);
+        }
+    } restore{prev};
+    hipStream_t s = (hipStream_t)stream;
+    sr_prolong *P = new (std::nothrow) sr_prolong();
+    if (!P) return rfail(SR_ENOMEM, "sr_prolong_create: out of host memory");
+    std::unique_ptr<sr_prolong> guard(P);
+    P->device = device;
+    P->nsph = nsph;
+    P->offc.assign(nsph + 1, 0);
+    P->offf.assign(nsph + 1, 0);
+    for (int m = 0; m < nsph; ++m) {
+        if (counts_c[m] < 1 || counts_f[m] < 1 || !(radii[m] > 0.0))
+            return rfail(SR_EINVAL, "sr_prolong_create: bad count or radius");
+        P->offc[m + 1] = P->offc[m] + counts_c[m];
+        P->offf[m + 1] = P->offf[m] + counts_f[m];
+    }
+    const int64_t NC = P->offc[nsph], NF = P->offf[nsph];
+    std::vector<double> hxc(3 * NC), hnc(3 * NC), hxf(3 * NF);
+    RHIP(hipMemcpyAsync(hxc.data(), xc, 3 * NC * sizeof(double), hipMemcpyDeviceToHost, s));
+    RHIP(hipMemcpyAsync(hnc.data(), nc, 3 * NC * sizeof(double), hipMemcpyDeviceToHost, s));
+    RHIP(hipMemcpyAsync(hxf.data(), xf, 3 * NF * sizeof(double), hipMemcpyDeviceToHost, s));
+    RHIP(hipStreamSynchronize(s));
+    P->idx.resize(nsph);
+    P->wts.resize(nsph);
+    for (int m = 0; m < nsph; ++m) {
+        const double *c = centers + 3 * m;
+        const int64_t oc = P->offc[m], nf = counts_f[m];
+        KeyMap keys = sphere_keys(&hxc[3 * oc], &hnc[3 * oc], counts_c[m], c, hc);
+        std::vector<double> x0, n0, b, w;
+        std::vector<int> id;
+        if (!sphere_targets(keys, c, radii[m], hc, &hxf[3 * P->offf[m]], nf, 0, 0, nullptr, x0, n0, b, id, w))
+            return rfail(SR_EINVAL, "sr_prolong_create: no interpolation stencil (is the coarse set the grid-line "
+                                    "quadrature of the spheres with spacing hc?)");
+        RHIP(P->idx[m].alloc(16 * nf));
+        RHIP(P->wts[m].alloc(16 * nf));
+        RHIP(hipMemcpyAsync(P->idx[m].p, id.data(), 16 * nf * sizeof(int), hipMemcpyHostToDevice, s));
+        RHIP(hipMemcpyAsync(P->wts[m].p, w.data(), 16 * nf * sizeof(double), hipMemcpyHostToDevice, s));
+        RHIP(hipStreamSynchronize(s));  // host staging vectors die at the end of the iteration
+    }
+    *out = guard.release();
+    return SR_OK;
+}
+
+sr_status sr_prolong_apply(sr_prolong *P, const double *qc, double *qf, void *stream)
+{
+    g_rerr.clear();
+    if (!P || !qc || !qf) return rfail(SR_EINVAL, "sr_prolong_apply: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    for (int m = 0; m < P->nsph; ++m) {
+        const int64_t nf = P->offf[m + 1] - P->offf[m];
+        hipLaunchKernelGGL(gather_q0_kernel, dim3(nblocks(nf)), dim3(256), 0, s, qc, nf, (int64_t)0, (int64_t)0,
+                           P->offc[m], P->idx[m].p, P->wts[m].p, qf + 3 * P->offf[m]);
+        RHIP(hipGetLastError());
+    }
+    return SR_OK;
+}
+
+sr_status sr_prolong_destroy(sr_prolong *P)
+{
+    g_rerr.clear();
+    if (!P) return SR_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(P->device);
+    (void)hipDeviceSynchronize();
+    delete P;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return SR_OK;
+}
 
 const char *sr_rigid_last_error(void) { return g_rerr.c_str(); }
 

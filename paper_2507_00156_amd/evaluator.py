@@ -140,7 +140,7 @@ class RigidSpheres:
         it, rr = B.sr_rigid_solve(self.r, rhs, x, x0 is not None, tol, maxit, restart, stream)
         return x, it, rr
 
-    def solve_refined(self, rhs, x0=None, tol=1e-10, inner_tol=1e-4, maxit=400, restart=60, stream=None):
+    def solve_refined(self, rhs, x0=None, tol=1e-10, inner_tol=1e-6, maxit=400, restart=60, stream=None):
         """Iterative refinement (FP64 residuals, working-precision GMRES corrections).
         Returns (x, inner iterations, outer corrections, FP64 relative residual)."""
         import torch
@@ -155,3 +155,99 @@ class RigidSpheres:
         u = torch.empty_like(y)
         B.sr_rigid_velocity(self.r, q, y, u, stream)
         return u
+
+
+class Prolongation:
+    """Coarse-to-fine interpolation of densities on spheres (sr_prolong_*)."""
+
+    def __init__(self, centers, radii, hc, counts_c, xc, nc, counts_f, xf, device: int = 0, stream=None):
+        self.p = B.sr_prolong_create(centers, radii, hc, counts_c, xc, nc, counts_f, xf, device, stream)
+        self.nf = int(xf.shape[0])
+
+    def __call__(self, qc, stream=None):
+        import torch
+
+        qf = torch.empty((self.nf, 3), dtype=torch.float64, device=qc.device)
+        B.sr_prolong_apply(self.p, qc, qf, stream)
+        return qf
+
+    def close(self) -> None:
+        if self.p is not None:
+            B.sr_prolong_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WarmStartNet:
+    """The warm-start network (sr_mlp_*): gap + 12 motion parameters -> coarse density."""
+
+    def __init__(self, width: int, nout: int, max_batch: int, passes: int = 3, g_mid: float = -2.760730458931123,
+                 g_half: float = 1.151292546497023, device: int = 0):
+        self.width, self.nout, self.max_batch = int(width), int(nout), int(max_batch)
+        self.net = B.sr_mlp_create(width, nout, max_batch, device)
+        self.nparam = B.sr_mlp_num_params(width, nout)
+        B.sr_mlp_set_options(self.net, passes, g_mid, g_half)
+
+    def close(self) -> None:
+        if self.net is not None:
+            B.sr_mlp_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_options(self, passes: int = 3, g_mid: float = -2.760730458931123, g_half: float = 1.151292546497023) -> None:
+        B.sr_mlp_set_options(self.net, passes, g_mid, g_half)
+
+    def set_params(self, flat) -> None:
+        B.sr_mlp_set_params(self.net, flat)
+
+    def get_params(self):
+        return B.sr_mlp_get_params(self.net, self.nparam)
+
+    def fit_output_scale(self, y, stream=None) -> None:
+        B.sr_mlp_fit_output_scale(self.net, y, stream)
+
+    def set_output_scale(self, s, stream=None) -> None:
+        B.sr_mlp_set_output_scale(self.net, s, stream)
+
+    def output_scale(self, stream=None):
+        import torch
+
+        s = torch.empty(self.nout, dtype=torch.float64, device="cuda")
+        B.sr_mlp_get_output_scale(self.net, s, stream)
+        return s
+
+    def forward(self, gap, motion, stream=None):
+        import torch
+
+        out = torch.empty((gap.shape[0], self.nout), dtype=torch.float32, device=gap.device)
+        B.sr_mlp_forward(self.net, gap, motion, out, stream)
+        return out
+
+    def predict(self, gap, motion, stream=None):
+        import torch
+
+        q = torch.empty((gap.shape[0], self.nout), dtype=torch.float64, device=gap.device)
+        B.sr_mlp_predict(self.net, gap, motion, q, stream)
+        return q
+
+    def gradients(self, gap, motion, y, idx=None, batch=None, stream=None):
+        import torch
+
+        g = torch.empty(self.nparam, dtype=torch.float32, device=gap.device)
+        b = int(gap.shape[0] if batch is None else batch)
+        loss = B.sr_mlp_gradients(self.net, b, idx, gap, motion, y, g, stream)
+        return g, loss
+
+    def train_step(self, gap, motion, y, lr, idx=None, batch=None, want_loss=True, stream=None):
+        b = int(gap.shape[0] if batch is None else batch)
+        return B.sr_mlp_train_step(self.net, b, idx, gap, motion, y, lr, want_loss, stream)

@@ -30,3 +30,12 @@ def warmstart_samples(n: int, seed: int, gap_range=GAP_RANGE):
     gaps = rng.uniform(gap_range[0], gap_range[1], size=n)
     motions = rng.standard_normal((n, 2, 6))
     return gaps, motions
+
+
+def warmstart_dataset(n_gaps: int, per_gap: int, seed: int, gap_range=GAP_RANGE):
+    """n_gaps gaps uniform in gap_range, each with per_gap motions (n_gaps * per_gap, 2, 6) ~ N(0, 1);
+    the gaps are repeated per_gap times in a row, so one geometry serves per_gap solves."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.uniform(gap_range[0], gap_range[1], size=n_gaps)
+    motions = rng.standard_normal((n_gaps * per_gap, 2, 6))
+    return np.repeat(gaps, per_gap), motions
