@@ -8,6 +8,17 @@ field and extrapolation FP64); the FP64 path is reported beside it.
 
 Prints ONE JSON line.  Metric: target-source interactions per second = 2 M N / t (each target-source
 pair counted once for the single layer and once for the double layer per extrapolated evaluation).
+
+Other workloads (--workload; each prints its own JSON line):
+  tree       ellipsoid (1, 0.8, 0.6), h = 1/128 (N = 169342, M = 189342), treecode far field (degree 8,
+             theta 0.7, leaf 2000), mixed precision; the direct sum timed beside it and the treecode's
+             error against the FP64 direct sum.
+  gmres      two unit spheres, h = 1/64 (136332 points), gaps 0.1, 0.05, 0.02, random rigid motions:
+             refined GMRES (mixed operator, FP64 residuals) to an FP64 relative residual of 1e-8.
+  mlp        the warm-start network at its real shape (width 256, 102420 outputs, batch 64): time of
+             a training step by phase, and of one inference.
+  warmstart  the learned warm start end to end: solves at h = 1/64 kept at the h = 1/32 points train
+             the network; held-out (gap, motion) pairs are solved from zero and from the prediction.
 """
 from __future__ import annotations
 
@@ -42,6 +53,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle baseline")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workload", choices=["c2", "tree", "gmres", "mlp", "warmstart"], default="c2")
+    ap.add_argument("--train-solves", type=int, default=800, help="warmstart: training solves")
+    ap.add_argument("--train-steps", type=int, default=60000, help="warmstart: optimizer steps")
+    ap.add_argument("--heldout", type=int, default=60, help="warmstart: held-out solves")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (calibrates the FETCH_SIZE / WRITE_SIZE "
                          "counters against known bytes) and exit")
@@ -115,6 +130,247 @@ def cpu_baseline(cfg, target_seconds):
             "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s"}
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def base_line(metric, value, unit, steps, warmup, ms, higher, dtype, data, config):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": data, "config": config}
+
+
+def bench_tree(a):
+    """Treecode far field at the ellipsoid h = 1/128 workload."""
+    import torch
+
+    import paper_2507_00156_amd as P
+    import workload
+
+    cfg = workload.build_config("c3")
+    s, t = cfg["surf"], cfg["targets"]
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()  # noqa: E731
+    args_dev = [dev(t.y), dev(t.x0), dev(t.n0), dev(t.b), dev(cfg["f0"]), dev(cfg["q0"])]
+    N, M = s.n, t.m
+    res, outs = {}, {}
+    for name, prec, far in (("tree", P.SR_MIXED, P.SR_TREE), ("direct", P.SR_MIXED, P.SR_DIRECT),
+                            ("direct_fp64", P.SR_FP64, P.SR_DIRECT)):
+        ev = P.Evaluator(cfg["h"], cfg["rho"], precision=prec, far_method=far, tree_degree=8, tree_theta=0.7,
+                         tree_leaf=2000)
+        ev.set_surface(dev(s.x), dev(s.normal), dev(s.w))
+        ev.set_density(P.SR_SL, dev(cfg["f"]))
+        ev.set_density(P.SR_DL, dev(cfg["q"]))
+        steps = a.steps if name == "tree" else max(2, a.steps // 5)
+        ms, wall, phases, out = time_eval(P, ev, args_dev, steps, 1, profile=True)
+        res[name] = dict(ms=ms, phases=phases, steps=steps)
+        outs[name] = [o.clone() for o in out[:2]]
+        log(f"[bench tree] {name}: {ms:.3f} ms/step, far {phases[0]:.3f} ms, near+extrap {phases[1]:.3f} ms")
+        ev.close()
+    ref = outs["direct_fp64"]
+
+    def rel(x, r):
+        return ((x - r).norm(dim=1).max() / r.norm(dim=1).max()).item()
+
+    ms = res["tree"]["ms"]
+    out = base_line("target-source interactions/s (extrapolated single+double layer, treecode far field)",
+                    2.0 * M * N / (ms / 1e3), "interactions/s", res["tree"]["steps"], 1, ms, True, "f32+f64",
+                    "synthetic (seeded ellipsoid quadrature, degree-4 harmonic densities, near targets)",
+                    {"workload": "ellipsoid (1,0.8,0.6), h=1/128: N=169342 sources, M=189342 targets, single+double "
+                                 "layer, rho=(2,3,4), cutoff 6, treecode degree 8, theta 0.7, leaf 2000, mixed",
+                     "n_sources": N, "n_targets": M})
+    out["roofline"] = None
+    out["phases_ms"] = {"far_tree": res["tree"]["phases"][0], "near_extrap": res["tree"]["phases"][1]}
+    out["direct_mixed_ms"] = res["direct"]["ms"]
+    out["direct_fp64_ms"] = res["direct_fp64"]["ms"]
+    out["speedup_vs_direct_mixed"] = res["direct"]["ms"] / ms
+    out["error_vs_fp64_direct"] = {"sl": rel(outs["tree"][0], ref[0]), "dl": rel(outs["tree"][1], ref[1])}
+    out["error_direct_mixed_vs_fp64_direct"] = {"sl": rel(outs["direct"][0], ref[0]),
+                                                "dl": rel(outs["direct"][1], ref[1])}
+    print(json.dumps(out), flush=True)
+
+
+def bench_gmres(a):
+    """Refined GMRES for two spheres at h = 1/64, one random rigid motion per gap."""
+    import torch
+
+    import workload
+    from paper_2507_00156_amd import warmstart as W
+
+    h = 1 / 64
+    per_gap = {}
+    mv_ms = None
+    for gap in (0.1, 0.05, 0.02):
+        sysm = W.TwoSpheres(h, gap, precision=1)
+        motion = workload.rigid_motion(np.random.default_rng(int(round(gap * 1000))))
+        b = sysm.R.rhs(motion)
+        if mv_ms is None:  # operator timing: mixed matrix-vector products
+            q = b.clone()
+            for _ in range(2):
+                sysm.R.matvec(q)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(max(3, a.steps // 4)):
+                sysm.R.matvec(q)
+            e1.record()
+            torch.cuda.synchronize()
+            mv_ms = e0.elapsed_time(e1) / max(3, a.steps // 4)
+        sysm.R.solve_refined(b, tol=1e-8, restart=100)  # builds the FP64 evaluators (set-up, untimed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, nout, rr = sysm.R.solve_refined(b, tol=1e-8, restart=100)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        per_gap[str(gap)] = {"seconds": dt, "inner_iterations": it, "fp64_corrections": nout, "fp64_relres": rr}
+        log(f"[bench gmres] gap {gap}: {dt:.2f} s, {it} inner iterations, {nout} passes, residual {rr:.1e}")
+        sysm.close()
+    ntot, nsph = 136332, 68166
+    mean_s = float(np.mean([v["seconds"] for v in per_gap.values()]))
+    out = base_line("seconds per two-sphere GMRES solve to FP64 relative residual 1e-8", mean_s, "s", 3, 1,
+                    mean_s * 1e3, False, "f32+f64",
+                    "synthetic (two unit spheres, grid-line quadrature, seeded random rigid motions)",
+                    {"workload": "two unit spheres, h=1/64 (136332 points, 408996 unknowns), gaps 0.1/0.05/0.02, "
+                                 "completed double layer, mixed operator with FP64 refinement, restart 100"})
+    out["roofline"] = None
+    out["per_gap"] = per_gap
+    out["matvec_ms_mixed"] = mv_ms
+    out["matvec_interactions_per_s"] = 2 * nsph * ntot / (mv_ms / 1e3)
+    print(json.dumps(out), flush=True)
+
+
+def bench_mlp(a):
+    """Training step and inference of the warm-start network at its real shape."""
+    import torch
+
+    import paper_2507_00156_amd as P
+    import workload
+
+    W_, nout, batch, n = 256, 102420, 64, 256
+    net = P.WarmStartNet(W_, nout, max_batch=batch, passes=3)
+    net.set_params(np.concatenate([v.ravel() for v in workload.mlp_init(W_, nout, 5).values()]).astype(np.float32))
+    rng = np.random.default_rng(1)
+    g, m = workload.warmstart_samples(n, 2)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()  # noqa: E731
+    gd, md, yd = dev(g), dev(m.reshape(n, 12)), dev(rng.standard_normal((n, nout)))
+    net.fit_output_scale(yd)
+    idxs = [torch.from_numpy(rng.integers(0, n, batch)).cuda() for _ in range(16)]
+    steps = max(50, a.steps * 10)
+    for i in range(a.warmup + 5):
+        net.train_step(gd, md, yd, 1e-4, idx=idxs[i % 16], batch=batch, want_loss=False)
+    torch.cuda.synchronize()
+    net.get_profile()
+    net.set_profiling(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        net.train_step(gd, md, yd, 1e-4, idx=idxs[i % 16], batch=batch, want_loss=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    net.set_profiling(False)
+    ph, ns = net.get_profile()
+    ph = [x / max(ns, 1) for x in ph]
+    # inference: one prediction
+    g1, m1 = gd[:1].contiguous(), md[:1].contiguous()
+    for _ in range(5):
+        net.predict(g1, m1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        net.predict(g1, m1)
+    e1.record()
+    torch.cuda.synchronize()
+    inf_ms = e0.elapsed_time(e1) / 50
+    nparam = net.nparam
+    adam_bytes = 28 * nparam  # theta, m, v read + written (24 B) and the gradient read (4 B)
+    achieved = adam_bytes / (ph[2] / 1e3) / 1e9
+    out = base_line("warm-start network training steps/s (batch 64)", 1e3 / (wall * 1e3 / steps), "steps/s", steps,
+                    a.warmup + 5, wall * 1e3 / steps, True, "bf16 (hi/lo, 3 products) + f32",
+                    "synthetic (random targets at the real shape)",
+                    {"workload": f"warm-start network: width 256, 4 layers, {nout} outputs, {nparam} parameters, "
+                                 "batch 64"})
+    out["roofline"] = {"bound": "hbm", "kernel": "adam_kernel (parameter update)", "achieved": achieved,
+                       "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+                       "bytes_per_launch": adam_bytes, "kernel_ms": ph[2]}
+    out["phases_ms_per_step"] = {"forward": ph[0], "backward": ph[1], "adam": ph[2], "weight_copies": ph[3]}
+    out["inference_ms_batch1"] = inf_ms
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
+def bench_warmstart(a):
+    """Data from the library's own solves, training, and held-out solves from zero and from the
+    learned warm start."""
+    import torch
+
+    import paper_2507_00156_amd as P
+    import workload
+    from paper_2507_00156_amd import warmstart as W
+
+    h_c, h_f, width = 1 / 32, 1 / 64, 256
+    per_gap = 4
+    gaps, motions = workload.warmstart_dataset(max(1, a.train_solves // per_gap), per_gap, seed=21)
+    t0 = time.perf_counter()
+    Y, its = W.generate(h_f, gaps, motions, tol=1e-6, log=log, keep=lambda g: W.restriction(h_c, h_f, g))
+    t_data = time.perf_counter() - t0
+    log(f"[bench warmstart] data: {len(gaps)} solves in {t_data:.0f} s (mean {its.mean():.1f} iterations)")
+    net = P.WarmStartNet(width, Y.shape[1], max_batch=64, passes=3)
+    net.set_params(np.concatenate([v.ravel() for v in workload.mlp_init(width, Y.shape[1], 5).values()])
+                   .astype(np.float32))
+    t0 = time.perf_counter()
+    hist = W.train(net, gaps, motions, Y, steps=a.train_steps, batch=64, lr=1e-3, seed=3, log=log,
+                   log_every=max(1, a.train_steps // 10))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del Y
+    ws = W.WarmStarter(net, h_c)
+    tg, tm = workload.warmstart_samples(a.heldout, 77)
+    rows = []
+    for i, (g, m) in enumerate(zip(tg, tm)):
+        fine = W.TwoSpheres(h_f, g, precision=1)
+        b = fine.R.rhs(m)
+        try:  # builds the FP64 evaluators (set-up, untimed); 3 iterations do not converge
+            fine.R.solve_refined(b, tol=1e-8, restart=100, maxit=3)
+        except P.SrError:
+            pass
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i0, _, r0 = fine.R.solve_refined(b, tol=1e-8, restart=100)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x0 = ws.guess(fine, m)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _, i1, _, r1 = fine.R.solve_refined(b, x0=x0, tol=1e-8, restart=100)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        rows.append((g, i0, i1, t1 - t0, t3 - t1, t2 - t1, r0, r1))
+        log(f"[bench warmstart] held-out {i + 1}/{len(tg)} gap {g:.4f}: zero start {i0} iterations ({t1 - t0:.2f} s), "
+            f"warm start {i1} ({t3 - t1:.2f} s incl. {1e3 * (t2 - t1):.1f} ms prediction)")
+        fine.close()
+    r = np.array(rows)
+    ratio = r[:, 1].mean() / r[:, 2].mean()
+    out = base_line("GMRES iterations from zero / from the learned warm start (FP64 residual 1e-8)", ratio,
+                    "x", len(rows), 0, float(r[:, 4].mean() * 1e3), True, "bf16 (hi/lo) network + f32/f64 solve",
+                    "synthetic (two unit spheres, seeded gaps U[0.02,0.2] and N(0,1) rigid motions)",
+                    {"workload": f"warm start: {len(gaps)} training solves at h=1/64 kept at the h=1/32 points "
+                                 f"(102420 outputs), width 256, {a.train_steps} Adam steps; {len(rows)} held-out "
+                                 "solves at h=1/64 to FP64 residual 1e-8"})
+    out["roofline"] = None
+    out["iterations_zero_mean"] = float(r[:, 1].mean())
+    out["iterations_warm_mean"] = float(r[:, 2].mean())
+    out["seconds_zero_mean"] = float(r[:, 3].mean())
+    out["seconds_warm_mean"] = float(r[:, 4].mean())
+    out["time_ratio"] = float(r[:, 3].mean() / r[:, 4].mean())
+    out["prediction_ms_mean"] = float(r[:, 5].mean() * 1e3)
+    out["max_final_residual"] = float(r[:, 6:8].max())
+    out["data_seconds"] = t_data
+    out["train_seconds"] = t_train
+    out["final_train_loss"] = hist[-1][1]
+    out["iterations_by_gap"] = [[float(x[0]), int(x[1]), int(x[2])] for x in rows]
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -124,6 +380,15 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
               "(the multi-GPU sharding is described in the design notes, not implemented)", file=sys.stderr)
         sys.exit(2)
+    if a.workload != "c2":
+        import torch
+
+        torch.cuda.init()  # the HIP runtime is initialized through torch before the library loads
+        import paper_2507_00156_amd as P
+
+        P.load_library()
+        {"tree": bench_tree, "gmres": bench_gmres, "mlp": bench_mlp, "warmstart": bench_warmstart}[a.workload](a)
+        return
     import torch
 
     import paper_2507_00156_amd as P

@@ -243,6 +243,15 @@ sr_status sr_mlp_gradients(sr_mlp *net, int batch, const int64_t *idx, int64_t n
 /* One Adam step with learning rate lr on the batch; *loss as above (the loss before the step). */
 sr_status sr_mlp_train_step(sr_mlp *net, int batch, const int64_t *idx, int64_t nrows, const double *gap,
                             const double *motion, const double *y, float lr, double *loss, void *stream);
+/* Profiling of training steps with HIP events on the step's stream: per step the phases
+ * SR_MLP_PHASE_FORWARD, _BACKWARD (loss and gradients), _ADAM (the parameter update, one kernel)
+ * and _COPIES (BF16 copies of the updated weights).  sr_mlp_get_profile waits for the recorded
+ * events, writes the accumulated milliseconds per phase and the number of profiled steps, and
+ * clears the record. */
+enum { SR_MLP_PHASE_FORWARD = 0, SR_MLP_PHASE_BACKWARD = 1, SR_MLP_PHASE_ADAM = 2, SR_MLP_PHASE_COPIES = 3,
+       SR_MLP_NPHASES = 4 };
+sr_status sr_mlp_set_profiling(sr_mlp *net, int on);
+sr_status sr_mlp_get_profile(sr_mlp *net, double *ms, int64_t *steps);
 /* The matrix-product kernel alone, for testing: C (m,n) = A (m,k) B^T with B (n,k), FP32 row-major
  * device arrays, through BF16 hi/lo operands and `passes` products.  Synchronizes `stream`. */
 sr_status sr_mlp_gemm_test(int device, int passes, int m, int n, int k, const float *a, const float *b, float *c,

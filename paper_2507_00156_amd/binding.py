@@ -27,7 +27,8 @@ EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_
            "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
            "sr_mlp_set_options", "sr_mlp_set_params", "sr_mlp_get_params", "sr_mlp_set_output_scale",
            "sr_mlp_fit_output_scale", "sr_mlp_get_output_scale", "sr_mlp_forward", "sr_mlp_predict",
-           "sr_mlp_gradients", "sr_mlp_train_step", "sr_mlp_gemm_test", "sr_mlp_last_error", "sr_last_error",
+           "sr_mlp_gradients", "sr_mlp_train_step", "sr_mlp_set_profiling", "sr_mlp_get_profile",
+           "sr_mlp_gemm_test", "sr_mlp_last_error", "sr_last_error",
            "sr_version")
 SR_PHASE_FAR, SR_PHASE_NEAR, SR_NPHASES = 0, 1, 2
 
@@ -97,13 +98,16 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_mlp_predict.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     L.sr_mlp_gradients.argtypes = [vp, C.c_int, vp, i64, vp, vp, vp, vp, d, vp]
     L.sr_mlp_train_step.argtypes = [vp, C.c_int, vp, i64, vp, vp, vp, C.c_float, d, vp]
+    L.sr_mlp_set_profiling.argtypes = [vp, C.c_int]
+    L.sr_mlp_get_profile.argtypes = [vp, d, C.POINTER(C.c_int64)]
     L.sr_mlp_gemm_test.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp]
     L.sr_mlp_last_error.argtypes = []
     L.sr_mlp_last_error.restype = C.c_char_p
     for fn in ("sr_prolong_create", "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_create", "sr_mlp_destroy",
                "sr_mlp_set_options", "sr_mlp_set_params", "sr_mlp_get_params", "sr_mlp_set_output_scale",
                "sr_mlp_fit_output_scale", "sr_mlp_get_output_scale", "sr_mlp_forward", "sr_mlp_predict",
-               "sr_mlp_gradients", "sr_mlp_train_step", "sr_mlp_gemm_test"):
+               "sr_mlp_gradients", "sr_mlp_train_step", "sr_mlp_set_profiling", "sr_mlp_get_profile",
+               "sr_mlp_gemm_test"):
         getattr(L, fn).restype = C.c_int
     L.sr_last_error.argtypes = []
     L.sr_last_error.restype = C.c_char_p
@@ -419,6 +423,21 @@ def sr_mlp_train_step(net, batch, idx, gap, motion, y, lr, want_loss=True, strea
         _tptr(motion, "motion", "f64"),
         _tptr(y, "y", "f64"), float(lr), C.byref(loss) if want_loss else None, _stream(stream)))
     return float(loss.value) if want_loss else None
+
+
+SR_MLP_NPHASES = 4
+
+
+def sr_mlp_set_profiling(net, on: bool) -> None:
+    _mcheck("sr_mlp_set_profiling", load_library().sr_mlp_set_profiling(net, int(bool(on))))
+
+
+def sr_mlp_get_profile(net):
+    """Returns ([ms forward, backward, adam, copies] summed over the profiled steps, steps)."""
+    ms = (C.c_double * SR_MLP_NPHASES)()
+    n = C.c_int64()
+    _mcheck("sr_mlp_get_profile", load_library().sr_mlp_get_profile(net, ms, C.byref(n)))
+    return list(ms), int(n.value)
 
 
 def sr_mlp_gemm_test(a, b, c, passes: int = 3, device: int = 0, stream=None) -> None:

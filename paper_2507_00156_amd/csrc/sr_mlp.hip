@@ -392,6 +392,9 @@ struct sr_mlp {
     float *part = nullptr;
     double *lpart = nullptr, *lval = nullptr;
     Bf bh1, bh2, bh3, bz, bdout, bda4, bd3, bd2;
+    // profiling of training steps: 5 events per step (start, forward, backward, Adam, weight copies)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool, ev_rec;
 
     template <typename T>
     hipError_t alloc(T **p, int64_t n)
@@ -575,6 +578,21 @@ struct DevGuard {
     }
 };
 
+sr_status mark(sr_mlp *M, hipStream_t s)
+{
+    if (!M->profiling) return SR_OK;
+    hipEvent_t e;
+    if (!M->ev_pool.empty()) {
+        e = M->ev_pool.back();
+        M->ev_pool.pop_back();
+    } else {
+        MHIP(hipEventCreate(&e));
+    }
+    M->ev_rec.push_back(e);
+    MHIP(hipEventRecord(e, s));
+    return SR_OK;
+}
+
 sr_status check_batch(sr_mlp *M, int B, const char *who)
 {
     if (!M) return mfail(SR_EINVAL, std::string(who) + ": NULL network");
@@ -701,6 +719,8 @@ sr_status sr_mlp_destroy(sr_mlp *M)
     DevGuard g(M->device);
     (void)hipDeviceSynchronize();
     for (void *p : M->allocs) (void)hipFree(p);
+    for (hipEvent_t e : M->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : M->ev_rec) (void)hipEventDestroy(e);
     delete M;
     return SR_OK;
 }
@@ -839,8 +859,11 @@ sr_status sr_mlp_train_step(sr_mlp *M, int B, const int64_t *idx, int64_t nrows,
     DevGuard g(M->device);
     hipStream_t s = (hipStream_t)stream;
     MSR(check_rows(idx, B, nrows, s, "sr_mlp_train_step"));
+    MSR(mark(M, s));
     MSR(forward(M, B, idx, gap, motion, s));
+    MSR(mark(M, s));
     MSR(backward(M, B, idx, motion, y, s));
+    MSR(mark(M, s));
     const double b1 = 0.9, b2 = 0.999;
     M->step += 1;
     const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)M->step)));
@@ -848,11 +871,43 @@ sr_status sr_mlp_train_step(sr_mlp *M, int B, const int64_t *idx, int64_t nrows,
     hipLaunchKernelGGL(adam_kernel, dim3(nblk(M->nparam)), dim3(256), 0, s, M->nparam, M->theta, M->mom, M->vel, M->grad,
                        lr, (float)b1, (float)b2, 1e-8f, c1, c2);
     MHIP(hipGetLastError());
+    MSR(mark(M, s));
     MSR(refresh_weights(M, s));
+    MSR(mark(M, s));
     if (loss) {
         MHIP(hipMemcpyAsync(loss, M->lval, sizeof(double), hipMemcpyDeviceToHost, s));
         MHIP(hipStreamSynchronize(s));
     }
+    return SR_OK;
+}
+
+sr_status sr_mlp_set_profiling(sr_mlp *M, int on)
+{
+    g_merr.clear();
+    if (!M) return mfail(SR_EINVAL, "sr_mlp_set_profiling: NULL network");
+    M->profiling = on != 0;
+    return SR_OK;
+}
+
+sr_status sr_mlp_get_profile(sr_mlp *M, double *ms, int64_t *steps)
+{
+    g_merr.clear();
+    if (!M || !ms || !steps) return mfail(SR_EINVAL, "sr_mlp_get_profile: NULL argument");
+    DevGuard g(M->device);
+    for (int k = 0; k < SR_MLP_NPHASES; ++k) ms[k] = 0.0;
+    *steps = 0;
+    const size_t per = SR_MLP_NPHASES + 1;
+    for (size_t i = 0; i + per <= M->ev_rec.size(); i += per) {
+        MHIP(hipEventSynchronize(M->ev_rec[i + per - 1]));
+        for (int k = 0; k < SR_MLP_NPHASES; ++k) {
+            float a = 0.f;
+            MHIP(hipEventElapsedTime(&a, M->ev_rec[i + k], M->ev_rec[i + k + 1]));
+            ms[k] += a;
+        }
+        *steps += 1;
+    }
+    for (hipEvent_t e : M->ev_rec) M->ev_pool.push_back(e);
+    M->ev_rec.clear();
     return SR_OK;
 }
 

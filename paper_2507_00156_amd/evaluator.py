@@ -248,6 +248,12 @@ class WarmStartNet:
         loss = B.sr_mlp_gradients(self.net, b, idx, gap, motion, y, g, stream)
         return g, loss
 
+    def set_profiling(self, on: bool) -> None:
+        B.sr_mlp_set_profiling(self.net, on)
+
+    def get_profile(self):
+        return B.sr_mlp_get_profile(self.net)
+
     def train_step(self, gap, motion, y, lr, idx=None, batch=None, want_loss=True, stream=None):
         b = int(gap.shape[0] if batch is None else batch)
         return B.sr_mlp_train_step(self.net, b, idx, gap, motion, y, lr, want_loss, stream)
