@@ -27,6 +27,9 @@ def lib():
         d = C.POINTER(C.c_double)
         i64 = C.c_int64
         L.orc_smoothing.argtypes = [C.c_double, d]
+        L.orc_smoothing_sharp.argtypes = [C.c_double, d]
+        L.orc_sl_sharp.argtypes = [i64, d, d, d, d, i64, d, d, d, C.c_double, d]
+        L.orc_dl_sharp.argtypes = [i64, d, d, d, d, i64, d, d, d, C.c_double, d]
         L.orc_I0.argtypes = [C.c_double]
         L.orc_I0.restype = C.c_double
         L.orc_I2.argtypes = [C.c_double]
@@ -61,6 +64,32 @@ def smoothing(t: float) -> np.ndarray:
     s = np.zeros(3)
     lib().orc_smoothing(float(t), _p(s))
     return s
+
+
+def smoothing_sharp(t: float) -> np.ndarray:
+    s = np.zeros(3)
+    lib().orc_smoothing_sharp(float(t), _p(s))
+    return s
+
+
+def sl_sharp(surf_x, surf_n, surf_w, f, y, n0, f0, delta):
+    """On-surface single layer with s1#, s2# at one delta (targets on the surface)."""
+    x, nn, w, f = _f64(surf_x), _f64(surf_n), _f64(surf_w), _f64(f)
+    y, n0, f0 = _f64(y), _f64(n0), _f64(f0)
+    out = np.zeros((y.shape[0], 3))
+    lib().orc_sl_sharp(x.shape[0], _p(x), _p(nn), _p(w), _p(f), y.shape[0], _p(y), _p(n0), _p(f0), float(delta),
+                       _p(out))
+    return out
+
+
+def dl_sharp(surf_x, surf_n, surf_w, q, y, n0, q0, delta):
+    """On-surface double layer with s2#, s3# at one delta, plus q(y)/2 (targets on the surface)."""
+    x, nn, w, q = _f64(surf_x), _f64(surf_n), _f64(surf_w), _f64(q)
+    y, n0, q0 = _f64(y), _f64(n0), _f64(q0)
+    out = np.zeros((y.shape[0], 3))
+    lib().orc_dl_sharp(x.shape[0], _p(x), _p(nn), _p(w), _p(q), y.shape[0], _p(y), _p(n0), _p(q0), float(delta),
+                       _p(out))
+    return out
 
 
 def I0(lam: float) -> float:

@@ -27,6 +27,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #ifdef _OPENMP
@@ -70,6 +71,48 @@ void orc_smoothing(double t, double s[3])
     s[0] = erf(t);
     s[1] = erf(t) - c * t * e;
     s[2] = erf(t) - c * (t + (2.0 / 3.0) * t * t * t) * e;
+}
+
+/* Paper section 2.1 (evaluation on the surface): the modified smoothing functions
+ *   s1#(t) = erf t + (2/(3 sqrt(pi))) (5t - 2t^3) e^{-t^2}
+ *   s2#(t) = erf t - (2/(3 sqrt(pi))) (3t - 14t^3 + 4t^5) e^{-t^2}
+ *   s3#(t) = erf t - (2/(9 sqrt(pi))) (9t + 6t^3 - 4t^5) e^{-t^2}
+ * that give O(delta^5) on the surface with one delta; 1 for t > 6 as in section 3.2. */
+void orc_smoothing_sharp(double t, double s[3])
+{
+    if (t > 6.0) {
+        s[0] = s[1] = s[2] = 1.0;
+        return;
+    }
+    double c = 2.0 / sqrt(PI);
+    if (t < 0.2) {
+        /* Maclaurin series: with e^{-t^2} = sum_m (-1)^m t^(2m) / m! and
+         * erf t = c sum_n (-1)^n t^(2n+1) / (n! (2n+1)), the coefficient of c t^(2n+1) is
+         *   s1#: E_n + (5 X_n - 2 X_{n-1}) / 3,
+         *   s2#: E_n - (3 X_n - 14 X_{n-1} + 4 X_{n-2}) / 3,
+         *   s3#: E_n - (9 X_n + 6 X_{n-1} - 4 X_{n-2}) / 9,
+         * E_n = (-1)^n / (n! (2n+1)), X_j = (-1)^j / j! (0 for j < 0).  The first term of s2# and the
+         * first two of s3# vanish exactly (s2# ~ t^3, s3# ~ t^5) and are left out. */
+        double X[16], a1 = 0.0, a2 = 0.0, a3 = 0.0, tp = t; /* tp = t^(2n+1) */
+        X[0] = 1.0;
+        for (int j = 1; j < 16; ++j) X[j] = -X[j - 1] / j;
+        for (int n = 0; n < 14; ++n) {
+            const double E = X[n] / (2 * n + 1);
+            const double x1 = n >= 1 ? X[n - 1] : 0.0, x2 = n >= 2 ? X[n - 2] : 0.0;
+            a1 += (E + (5.0 * X[n] - 2.0 * x1) / 3.0) * tp;
+            if (n >= 1) a2 += (E - (3.0 * X[n] - 14.0 * x1 + 4.0 * x2) / 3.0) * tp;
+            if (n >= 2) a3 += (E - (9.0 * X[n] + 6.0 * x1 - 4.0 * x2) / 9.0) * tp;
+            tp *= t * t;
+        }
+        s[0] = c * a1;
+        s[1] = c * a2;
+        s[2] = c * a3;
+        return;
+    }
+    double e = exp(-t * t), t3 = t * t * t, t5 = t3 * t * t;
+    s[0] = erf(t) + (c / 3.0) * (5.0 * t - 2.0 * t3) * e;
+    s[1] = erf(t) - (c / 3.0) * (3.0 * t - 14.0 * t3 + 4.0 * t5) * e;
+    s[2] = erf(t) - (c / 9.0) * (9.0 * t + 6.0 * t3 - 4.0 * t5) * e;
 }
 
 /* Paper section 2, eq. (I0): I0(lambda) = e^{-lambda^2}/sqrt(pi) - |lambda| erfc|lambda|. */
@@ -142,9 +185,9 @@ int orc_extrapolate(double b, double h, const double rho[3], const double ud[9],
  *   u_i^delta(y) = (1/8pi) sum_p S^delta_ij(y, x_p) [f_j(x_p) - f_k(x0) n_k(x0) n_j(x_p)] w_p,
  *   S^delta_ij = delta_ij s1(r/delta)/r + (y_i - x_i)(y_j - x_j) s2(r/delta)/r^3.
  * out: (m,3). */
-void orc_sl_delta(int64_t n, const double *x, const double *nrm, const double *w, const double *f,
-                  int64_t m, const double *y, const double *n0, const double *f0, double delta,
-                  double *out)
+static void sl_delta_kind(int64_t n, const double *x, const double *nrm, const double *w, const double *f,
+                          int64_t m, const double *y, const double *n0, const double *f0, double delta,
+                          int sharp, double *out)
 {
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t it = 0; it < m; ++it) {
@@ -159,12 +202,17 @@ void orc_sl_delta(int64_t n, const double *x, const double *nrm, const double *w
                 g[k] = (f[3 * p + k] - c * nrm[3 * p + k]) * w[p];
             }
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (r == 0.0) { /* limit of s1(r/delta)/r; the d d s2/r^3 term vanishes */
-                for (int i = 0; i < 3; ++i) acc[i] += 2.0 / (sqrt(PI) * delta) * g[i];
+            if (r == 0.0) { /* limit of s1(r/delta)/r (2/sqrt(pi), or 16/(3 sqrt(pi)) for s1#) / delta;
+                               the d d s2/r^3 term vanishes */
+                const double lim = (sharp ? 16.0 / 3.0 : 2.0) / (sqrt(PI) * delta);
+                for (int i = 0; i < 3; ++i) acc[i] += lim * g[i];
                 continue;
             }
             double s[3];
-            orc_smoothing(r / delta, s);
+            if (sharp)
+                orc_smoothing_sharp(r / delta, s);
+            else
+                orc_smoothing(r / delta, s);
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
                     double S = (i == j ? 1.0 : 0.0) * s[0] / r + d[i] * d[j] * s[1] / (r * r * r);
@@ -173,6 +221,23 @@ void orc_sl_delta(int64_t n, const double *x, const double *nrm, const double *w
         }
         for (int i = 0; i < 3; ++i) out[3 * it + i] = acc[i] / (8.0 * PI);
     }
+}
+
+void orc_sl_delta(int64_t n, const double *x, const double *nrm, const double *w, const double *f,
+                  int64_t m, const double *y, const double *n0, const double *f0, double delta,
+                  double *out)
+{
+    sl_delta_kind(n, x, nrm, w, f, m, y, n0, f0, delta, 0, out);
+}
+
+/* On-surface single layer with the modified smoothing (section 2.1): the regularized sum of eqs.
+ * (Stokes_SL2), (Sreg) with s1#, s2# at one delta, no extrapolation.  Targets y on the surface
+ * (y = x0), n0 their normals, f0 = f(y).  out: (m,3). */
+void orc_sl_sharp(int64_t n, const double *x, const double *nrm, const double *w, const double *f,
+                  int64_t m, const double *y, const double *n0, const double *f0, double delta,
+                  double *out)
+{
+    sl_delta_kind(n, x, nrm, w, f, m, y, n0, f0, delta, 1, out);
 }
 
 /* Regularized double layer at one delta, WITHOUT the chi q(x0) term, paper eqs. (Stokes_DL2),
@@ -217,6 +282,40 @@ void orc_dl_delta(int64_t n, const double *x, const double *nrm, const double *w
                     }
         }
         for (int i = 0; i < 3; ++i) out[3 * it + i] = acc[i] / (8.0 * PI);
+    }
+}
+
+/* On-surface double layer with the modified smoothing (section 2.1): the stresslet of eq. (Stresslet)
+ * with its factor 1/r^5 replaced by s3#(r/delta)/r^5 (eq. (Treg) with s3 -> s3#), at one delta,
+ * applied to the subtracted density of eq. (Stokes_DL1), plus q(y)/2 (chi = 1/2 on the surface):
+ *   v_i(y) = (1/8pi) sum_p -6 d_i d_j d_k s3#(r/delta)/r^5 [q_j(x_p) - q_j(y)] n_k(x_p) w_p + q_i(y)/2,
+ * d = y - x_p.  (The split of eq. (Tsplit) serves the extrapolated off-surface values: on the surface
+ * its t1 part is multiplied by s2 - s3, which vanishes for the original factors only.)  out: (m,3). */
+void orc_dl_sharp(int64_t n, const double *x, const double *nrm, const double *w, const double *q,
+                  int64_t m, const double *y, const double *n0, const double *q0, double delta, double *out)
+{
+    (void)n0;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t it = 0; it < m; ++it) {
+        const double *yt = y + 3 * it;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t p = 0; p < n; ++p) {
+            double d[3], a[3], mw[3];
+            for (int k = 0; k < 3; ++k) {
+                d[k] = yt[k] - x[3 * p + k];
+                a[k] = q[3 * p + k] - q0[3 * it + k];
+                mw[k] = nrm[3 * p + k] * w[p];
+            }
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r == 0.0) continue; /* d = 0 and q - q0 = 0: the term vanishes */
+            double s[3];
+            orc_smoothing_sharp(r / delta, s);
+            double r5 = r * r * r * r * r;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    for (int k = 0; k < 3; ++k) acc[i] += -6.0 * d[i] * d[j] * d[k] * s[2] / r5 * a[j] * mw[k];
+        }
+        for (int i = 0; i < 3; ++i) out[3 * it + i] = acc[i] / (8.0 * PI) + 0.5 * q0[3 * it + i];
     }
 }
 
