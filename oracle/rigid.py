@@ -22,6 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import dl as _dl
+from . import dl_sharp as _dl_sharp
 
 PI = np.pi
 THETA = np.deg2rad(70.0)
@@ -105,10 +106,13 @@ def _lagrange(s, wdt):
 class RigidProblem:
     """Targets = all quadrature points of all spheres, in sphere order."""
 
-    def __init__(self, spheres, h, rho=(2.0, 3.0, 4.0), full=True):
+    def __init__(self, spheres, h, rho=(2.0, 3.0, 4.0), full=True, sharp=False, sharp_rho=3.0):
         self.S = spheres
         self.h = h
         self.rho = tuple(rho)
+        # sharp: a sphere's own points (on its surface) use the modified smoothing at sharp_rho h
+        # (paper section 2.1) instead of the extrapolation
+        self.sharp, self.sharp_rho = bool(sharp), float(sharp_rho)
         self.y = np.concatenate([s.x for s in spheres])
         self.off = np.cumsum([0] + [s.size for s in spheres])
         self.ntot = int(self.off[-1])
@@ -153,13 +157,23 @@ class RigidProblem:
             out += (Sf + np.cross(Lm, d) / r ** 3) / (8 * PI)
         return out
 
+    def _layer(self, s, qm, y, x0, n0, b, q0, own):
+        """Double layer of sphere s at targets y; rows `own` are its own points."""
+        if not self.sharp or not own.any():
+            return _dl(s.x, s.n, s.w, qm, y, x0, n0, b, q0, self.h, self.rho)
+        out = np.empty((len(y), 3))
+        out[own] = _dl_sharp(s.x, s.n, s.w, qm, y[own], n0[own], q0[own], self.sharp_rho * self.h)
+        if (~own).any():
+            out[~own] = _dl(s.x, s.n, s.w, qm, y[~own], x0[~own], n0[~own], b[~own], q0[~own], self.h, self.rho)
+        return out
+
     def double_layers(self, q):
         out = np.zeros((self.ntot, 3))
         for s, qm, cr in zip(self.S, self.split(q), self.cross):
             q0 = np.empty((self.ntot, 3))
             q0[cr["own"]] = qm
             q0[~cr["own"]] = np.einsum("ks,ksc->kc", cr["wts"], qm[cr["idx"]])
-            out += _dl(s.x, s.n, s.w, qm, self.y, cr["x0"], cr["n0"], cr["b"], q0, self.h, self.rho)
+            out += self._layer(s, qm, self.y, cr["x0"], cr["n0"], cr["b"], q0, cr["own"])
         return out
 
     def matvec(self, q):
@@ -183,7 +197,7 @@ class RigidProblem:
             if (~own).any():
                 idx, wts = s.stencils(x0[~own])
                 q0[~own] = np.einsum("ks,ksc->kc", wts, qm[idx])
-            out += _dl(s.x, s.n, s.w, qm, y, x0, n0, b, q0, self.h, self.rho)
+            out += self._layer(s, qm, y, x0, n0, b, q0, own)
         return out
 
     def velocity(self, q, y):
