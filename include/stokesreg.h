@@ -70,6 +70,12 @@ typedef struct {
     int tree_degree;    /* treecode: Chebyshev interpolation degree p (1..16)                     */
     double tree_theta;  /* treecode: multipole acceptance parameter theta, MAC r_c / R <= theta   */
     int tree_leaf;      /* treecode: maximum number of points in a leaf N0 (>= 1)                 */
+    int surface_sharp;  /* 1: targets ON the surface (b == 0) use the modified smoothing functions
+                           s1#, s2#, s3# of paper section 2.1 at the single delta sharp_rho h, with no
+                           extrapolation (single layer: eq. (Sreg) with s1#, s2#; double layer: the
+                           stresslet with s3#(r/delta)/r^5 in place of 1/r^5); other targets are
+                           extrapolated as usual.  0 (default): every target is extrapolated.      */
+    double sharp_rho;   /* delta / h of the modified smoothing (> 0); default 3                     */
 } sr_params;
 
 /* Fill *p with defaults: h = 0 (must be set), rho = (2,3,4), cutoff = 6, SR_FP64, SR_DIRECT,

@@ -36,7 +36,7 @@ SR_PHASE_FAR, SR_PHASE_NEAR, SR_NPHASES = 0, 1, 2
 class SrParams(C.Structure):
     _fields_ = [("h", C.c_double), ("rho", C.c_double * 3), ("cutoff", C.c_double), ("precision", C.c_int),
                 ("far_method", C.c_int), ("tree_degree", C.c_int), ("tree_theta", C.c_double),
-                ("tree_leaf", C.c_int)]
+                ("tree_leaf", C.c_int), ("surface_sharp", C.c_int), ("sharp_rho", C.c_double)]
 
 
 class SrError(RuntimeError):

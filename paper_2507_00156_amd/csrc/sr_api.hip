@@ -102,6 +102,7 @@ struct sr_ctx {
     DevBuf<Pos4<double>> pos64;
     DevBuf<Pos4<float>> pos32;
     DevBuf<double> part;  // far-field partial sums
+    DevBuf<FrontierRec> t_front;
 
     CellGrid grid{};
     double grid_rnear = -1.0;
@@ -143,6 +144,7 @@ struct sr_ctx {
         pos64.release();
         pos32.release();
         part.release();
+        t_front.release();
         t_nodes.release();
         t_item_node.release();
         t_item_begin.release();
@@ -168,7 +170,9 @@ namespace {
 
 double near_radius(const sr_params &p)
 {
-    return p.cutoff * std::max(p.rho[0], std::max(p.rho[1], p.rho[2])) * p.h;
+    double r = std::max(p.rho[0], std::max(p.rho[1], p.rho[2]));
+    if (p.surface_sharp) r = std::max(r, p.sharp_rho);
+    return p.cutoff * r * p.h;
 }
 
 // Uniform grid of cells of side >= the near radius (plus a relative margin of 1e-5, so that a pair
@@ -294,6 +298,9 @@ sr_status ensure_tree(sr_ctx *c, hipStream_t s)
         SR_HIP(hipMemcpyAsync(c->t_node_item0.p, T.node_item0.data(), (nn + 1) * sizeof(int), hipMemcpyHostToDevice,
                               s));
         SR_HIP(hipMemcpyAsync(c->t_perm.p, T.order.data(), c->n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        SR_HIP(c->t_front.reserve(T.front.size()));
+        SR_HIP(hipMemcpyAsync(c->t_front.p, T.front.data(), T.front.size() * sizeof(FrontierRec),
+                              hipMemcpyHostToDevice, s));
         SR_HIP(hipMemcpyAsync(c->t_prox64.p, p64.data(), p64.size() * sizeof(ProxRec<double>), hipMemcpyHostToDevice,
                               s));
         SR_HIP(hipMemcpyAsync(c->t_prox32.p, p32.data(), p32.size() * sizeof(ProxRec<float>), hipMemcpyHostToDevice,
@@ -314,6 +321,8 @@ sr_status ensure_tree(sr_ctx *c, hipStream_t s)
         D.nprox = nprox;
         D.p = p;
         D.stack_cap = 7 * T.depth + 2;
+        D.front = c->t_front.p;
+        D.nfront = (int)T.front.size();
         c->tree_p = p;
         c->tree_leaf = leaf;
         c->tree_dirty = false;
@@ -360,6 +369,8 @@ void sr_default_params(sr_params *p)
     p->tree_degree = 8;
     p->tree_theta = 0.7;
     p->tree_leaf = 2000;
+    p->surface_sharp = 0;
+    p->sharp_rho = 3.0;
 }
 
 const char *sr_last_error(void) { return g_err.c_str(); }
@@ -417,6 +428,10 @@ sr_status sr_set_params(sr_ctx *c, const sr_params *p)
             return fail(SR_EINVAL, "sr_set_params: tree_theta must be in [0, 1)");
         if (p->tree_leaf < 1) return fail(SR_EINVAL, "sr_set_params: tree_leaf must be >= 1");
     }
+    if (p->surface_sharp != 0 && p->surface_sharp != 1)
+        return fail(SR_EINVAL, "sr_set_params: surface_sharp must be 0 or 1");
+    if (p->surface_sharp && !is_pos_finite(p->sharp_rho))
+        return fail(SR_EINVAL, "sr_set_params: sharp_rho must be positive");
     c->prm = *p;
     c->have_params = true;
     return SR_OK;
@@ -539,6 +554,8 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     dp.cutoff = c->prm.cutoff;
     dp.rnear = c->grid_rnear;
     dp.precision = c->prm.precision;
+    dp.sharp = c->prm.surface_sharp ? 1 : 0;
+    dp.inv_dsharp = 1.0 / (c->prm.sharp_rho * c->prm.h);
 
     const bool tree = c->prm.far_method == SR_TREE;
     int nparts = kFarSplits;
@@ -557,7 +574,7 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
         D.order = c->t_order.p;
         D.sort_tmp = c->t_sort_tmp.p;
         D.sort_tmp_bytes = c->t_sort_tmp.cap;
-        nparts = 1;
+        nparts = c->tdev.nfront;
     }
     SR_HIP(c->part.reserve((size_t)nparts * 6 * (size_t)m));
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;

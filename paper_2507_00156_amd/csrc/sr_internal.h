@@ -83,8 +83,10 @@ struct DevParams {
     double inv_delta[3];
     int ord[3];
     double cutoff;       // in t = r / delta
-    double rnear;        // cutoff * max_j delta_j
+    double rnear;        // cutoff * max_j delta_j (and the modified-smoothing delta if larger)
     int precision;
+    int sharp;           // targets on the surface (b == 0) use the modified smoothing at one delta
+    double inv_dsharp;   // 1 / that delta
 };
 
 // ---- kernel launchers (return hipSuccess or the launch error) ----

@@ -136,6 +136,77 @@ __device__ __forceinline__ void series3(double t, double &s1, double &s2, double
     s3 = ct * t2 * t2 * b3;
 }
 
+// Modified smoothing for targets on the surface (section 2.1), with erf t = 1 - e^{-t^2} erfcx(t):
+//   s1# = 1 - E (R - (c/3)(5t - 2t^3)),  s2# = 1 - E (R + (c/3)(3t - 14t^3 + 4t^5)),
+//   s3# = 1 - E (R + (c/9)(9t + 6t^3 - 4t^5)),  c = 2/sqrt(pi), R = erfcx(t);
+// 1 beyond the cut-off, 0 below kSeriesT (added by the series pass).
+__device__ __forceinline__ void smoothing3_sharp(double t, double cutoff, double &s1, double &s2, double &s3)
+{
+    using namespace erfcx_poly;
+    const double E = exp(-t * t);
+    const double tc = fmin(t, 6.25);
+    const double den = tc + kL;
+    double inv = __builtin_amdgcn_rcp(den);
+    double e = __builtin_fma(-den, inv, 1.0);
+    inv = __builtin_fma(inv, e, inv);
+    e = __builtin_fma(-den, inv, 1.0);
+    inv = __builtin_fma(inv, e, inv);
+    const double x = __builtin_fma(kA, (tc - kL) * inv, kB);
+    double pz = kC[kDegree];
+#pragma unroll
+    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, kC[k]);
+    const double R = kL * inv * pz;
+    const double t2 = t * t, c3 = kTwoOverSqrtPi / 3.0, c9 = kTwoOverSqrtPi / 9.0;
+    const double P1 = R - c3 * t * __builtin_fma(-2.0, t2, 5.0);
+    const double P2 = __builtin_fma(c3 * t, __builtin_fma(t2, __builtin_fma(4.0, t2, -14.0), 3.0), R);
+    const double P3 = __builtin_fma(c9 * t, __builtin_fma(t2, __builtin_fma(-4.0, t2, 6.0), 9.0), R);
+    const double Ec = t > cutoff ? 0.0 : E;
+    const bool ser = t < kSeriesT;
+    s1 = ser ? 0.0 : __builtin_fma(-Ec, P1, 1.0);
+    s2 = ser ? 0.0 : __builtin_fma(-Ec, P2, 1.0);
+    s3 = ser ? 0.0 : __builtin_fma(-Ec, P3, 1.0);
+}
+
+// Maclaurin coefficients of the modified functions: s1# = c t sum A1_n t^2n, s2# = c t^3 sum A2_n t^2n,
+// s3# = c t^5 sum A3_n t^2n; from erf t = c sum E_n t^(2n+1), E_n = (-1)^n / (n! (2n+1)), and
+// t^(2j+1) e^{-t^2} = sum X_m t^(2m+2j+1), X_m = (-1)^m / m!; the vanishing leading terms of s2#
+// (one) and s3# (two) are left out.
+struct SharpSeriesCoef {
+    double a1[kSeriesN], a2[kSeriesN], a3[kSeriesN];
+};
+constexpr SharpSeriesCoef make_sharp_series()
+{
+    SharpSeriesCoef c{};
+    double X[kSeriesN + 3] = {};
+    X[0] = 1.0;
+    for (int j = 1; j < kSeriesN + 3; ++j) X[j] = -X[j - 1] / j;
+    for (int n = 0; n < kSeriesN + 2; ++n) {
+        const double E = X[n] / (2 * n + 1);
+        const double x1 = n >= 1 ? X[n - 1] : 0.0, x2 = n >= 2 ? X[n - 2] : 0.0;
+        if (n < kSeriesN) c.a1[n] = E + (5.0 * X[n] - 2.0 * x1) / 3.0;
+        if (n >= 1 && n - 1 < kSeriesN) c.a2[n - 1] = E - (3.0 * X[n] - 14.0 * x1 + 4.0 * x2) / 3.0;
+        if (n >= 2 && n - 2 < kSeriesN) c.a3[n - 2] = E - (9.0 * X[n] + 6.0 * x1 - 4.0 * x2) / 9.0;
+    }
+    return c;
+}
+__constant__ constexpr SharpSeriesCoef kSharpSeries = make_sharp_series();
+
+__device__ __forceinline__ void series3_sharp(double t, double &s1, double &s2, double &s3)
+{
+    const double t2 = t * t;
+    double b1 = kSharpSeries.a1[kSeriesN - 1], b2 = kSharpSeries.a2[kSeriesN - 1], b3 = kSharpSeries.a3[kSeriesN - 1];
+#pragma unroll 1
+    for (int n = kSeriesN - 2; n >= 0; --n) {
+        b1 = __builtin_fma(b1, t2, kSharpSeries.a1[n]);
+        b2 = __builtin_fma(b2, t2, kSharpSeries.a2[n]);
+        b3 = __builtin_fma(b3, t2, kSharpSeries.a3[n]);
+    }
+    const double ct = kTwoOverSqrtPi * t;
+    s1 = ct * b1;
+    s2 = ct * t2 * b2;
+    s3 = ct * t2 * t2 * b3;
+}
+
 __device__ __forceinline__ double pick3(const double (&v)[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
 
 struct Target {
@@ -279,7 +350,74 @@ __device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict_
     }
 }
 
-template <typename TC, bool SL, bool DL>
+// A near pair of a target on the surface evaluated with the modified smoothing at one delta
+// (section 2.1): single layer with s1#, s2# (eq. (Sreg)); double layer with the stresslet's 1/r^5
+// replaced by s3#/r^5, accumulated as sum d (d.a)(d.m) s3#/r^5 like the far-field channel.  Sums go to
+// A.sl[0], A.dl[0].  SER as in near_pair.
+template <bool SL, bool DL, bool SER>
+__device__ __forceinline__ bool near_pair_sharp(const SrcRec<double> &s, const Target &T, const DevParams &p,
+                                                Acc &A)
+{
+    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double gx = 0, gy = 0, gz = 0;
+    if (SL) {
+        gx = s.fw[0] - T.c * s.nw[0];
+        gy = s.fw[1] - T.c * s.nw[1];
+        gz = s.fw[2] - T.c * s.nw[2];
+    }
+    if (r2 == 0.0) {
+        // limit of s1#(r/delta)/r: 16/(3 sqrt(pi) delta); the other terms vanish
+        if (SL && !SER) {
+            const double l = (8.0 / 3.0) * kTwoOverSqrtPi * p.inv_dsharp;
+            A.sl[0][0] += gx * l;
+            A.sl[0][1] += gy * l;
+            A.sl[0][2] += gz * l;
+        }
+        return false;
+    }
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    const double t = r * p.inv_dsharp;
+    if (SER && !(t < kSeriesT)) return false;
+    double s1, s2, s3;
+    if (SER)
+        series3_sharp(t, s1, s2, s3);
+    else
+        smoothing3_sharp(t, p.cutoff, s1, s2, s3);
+    const double ir2 = ir * ir;
+    const double ir3 = ir2 * ir;
+    if (SL) {
+        const double dg = dx * gx + dy * gy + dz * gz;
+        const double k1 = s1 * ir, k2 = dg * s2 * ir3;
+        A.sl[0][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[0][0]));
+        A.sl[0][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[0][1]));
+        A.sl[0][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[0][2]));
+    }
+    if (DL) {
+        const double ax = s.q[0] - T.q0[0], ay = s.q[1] - T.q0[1], az = s.q[2] - T.q0[2];
+        const double da = dx * ax + dy * ay + dz * az;
+        const double dm = dx * s.nw[0] + dy * s.nw[1] + dz * s.nw[2];
+        const double co = da * dm * s3 * (ir3 * ir2);
+        A.dl[0][0] = __builtin_fma(dx, co, A.dl[0][0]);
+        A.dl[0][1] = __builtin_fma(dy, co, A.dl[0][1]);
+        A.dl[0][2] = __builtin_fma(dz, co, A.dl[0][2]);
+    }
+    return !SER && t < kSeriesT;
+}
+
+template <bool SL, bool DL>
+__device__ __forceinline__ void near_pair_sharp_full(const SrcRec<double> *__restrict__ rec64, int k,
+                                                     const Target &T, const DevParams &p, Acc &A)
+{
+    if (near_pair_sharp<SL, DL, false>(rec64[k], T, p, A)) {
+        int kk = k;
+        asm volatile("" : "+v"(kk));
+        near_pair_sharp<SL, DL, true>(rec64[kk], T, p, A);
+    }
+}
+
+template <typename TC, bool SL, bool DL, bool SHARP>
 __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
                                                                const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
@@ -304,6 +442,12 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
         T.q0[i] = DL ? a.q0[3 * t + i] : 0.0;
     }
     T.b = a.b[t];
+    // a target on the surface with the modified smoothing selected: one delta, no extrapolation
+    // (wavefront-uniform: one target per wavefront)
+    // SHARP instances take exactly these targets, the others every other target, so that each
+    // instance is compiled for one path (one register budget)
+    const bool sharp = p.sharp && T.b == 0.0;
+    if (sharp != SHARP) return;  // wavefront-uniform exit
     T.c = SL ? a.f0[3 * t] * T.n[0] + a.f0[3 * t + 1] * T.n[1] + a.f0[3 * t + 2] * T.n[2] : 0.0;
     const TC tyx = (TC)(T.y[0] - a.org[0]), tyy = (TC)(T.y[1] - a.org[1]), tyz = (TC)(T.y[2] - a.org[2]);
 
@@ -349,13 +493,21 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
                     if (lane + kWave < cnt) queue[lane] = queue[lane + kWave];
                     cnt -= kWave;
                     wave_lds_sync();
-                    near_pair_full<SL, DL>(rec64, k2, T, p, A);
+                    if (SHARP)
+                        near_pair_sharp_full<SL, DL>(rec64, k2, T, p, A);
+                    else
+                        near_pair_full<SL, DL>(rec64, k2, T, p, A);
                 }
             }
         }
     }
     wave_lds_sync();
-    if (lane < cnt) near_pair_full<SL, DL>(rec64, queue[lane], T, p, A);
+    if (lane < cnt) {
+        if (SHARP)
+            near_pair_sharp_full<SL, DL>(rec64, queue[lane], T, p, A);
+        else
+            near_pair_full<SL, DL>(rec64, queue[lane], T, p, A);
+    }
 
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -369,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
     const double b = T.b;
     double w0 = 1.0, w1 = 0.0, w2 = 0.0;
     const double dmax = p.rho[2] * p.h;  // largest delta (sorted)
-    if (fabs(b) < p.cutoff * dmax) {
+    if (!SHARP && fabs(b) < p.cutoff * dmax) {
         double al[3], be[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -399,7 +551,7 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
             a.u[3 * t + i] = w0 * uj[0] + w1 * uj[1] + w2 * uj[2];
             if (a.u_delta)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * p.ord[j] + i] = uj[j];
+                for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * p.ord[j] + i] = SHARP ? uj[0] : uj[j];
         }
         if (DL) {
             double far = 0.0;
@@ -410,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
             a.v[3 * t + i] = w0 * vj[0] + w1 * vj[1] + w2 * vj[2] + chi * pick3(T.q0, i);
             if (a.v_delta)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * p.ord[j] + i] = vj[j];
+                for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * p.ord[j] + i] = SHARP ? vj[0] : vj[j];
         }
     }
 }
@@ -421,8 +573,12 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
 {
     const int per_block = kBlock / kWave;
     const int64_t blocks = (a.m + per_block - 1) / per_block;
-    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64, pos,
-                       cell_start, g, a, p, rc2, part, nparts);
+    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64,
+                       pos, cell_start, g, a, p, rc2, part, nparts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !p.sharp) return e;
+    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64,
+                       pos, cell_start, g, a, p, rc2, part, nparts);
     return hipGetLastError();
 }
 

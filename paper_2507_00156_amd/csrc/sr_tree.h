@@ -29,12 +29,22 @@ struct alignas(16) ProxRec {
     T pad2;
 };
 
+// One cluster of the frontier (a cut of the tree that splits the walk): its ancestors, root first, and
+// bit j of `first` set when it is the first frontier cluster below anc[j].
+constexpr int kMaxFrontier = 8;
+constexpr int kMaxFrontierDepth = 8;
+struct FrontierRec {
+    int node, nanc, first;
+    int anc[kMaxFrontierDepth];
+};
+
 struct TreeHost {
     std::vector<TreeNode> nodes;
     std::vector<int64_t> order;      // tree order -> caller index
     std::vector<double> cosk;        // cos(k pi / p)
     std::vector<double> proxy_xyz;   // [node][proxy][3]
     std::vector<int> item_node, item_begin, item_end, node_item0;
+    std::vector<FrontierRec> front;
     int p = 0, depth = 0;
 };
 
@@ -50,7 +60,8 @@ struct TreeDev {
     int *idx_in = nullptr, *order = nullptr;
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
-    int nnodes = 0, nitems = 0, nprox = 0, p = 0, stack_cap = 0;
+    FrontierRec *front = nullptr;
+    int nnodes = 0, nitems = 0, nprox = 0, p = 0, stack_cap = 0, nfront = 1;
 };
 
 // Build the octree (host), its proxy points and anterpolation items.  hx: (n,3) caller order.
@@ -65,7 +76,7 @@ hipError_t launch_anterp(const TreeDev &D, const double *cosk, double *partial, 
 hipError_t launch_target_order(const double *y, int m, const double lo[3], double inv, TreeDev &D, hipStream_t s);
 size_t target_sort_tmp_bytes(int m);
 
-// Far field by the treecode into part[channel][target] (one split).
+// Far field by the treecode into part[split][channel][target], D.nfront splits.
 hipError_t launch_tree_far(int precision, int layers, const TreeDev &D, const EvalArgs &a, double theta,
                            double rnear, double *part, hipStream_t s);
 

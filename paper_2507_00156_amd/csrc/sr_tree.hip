@@ -22,8 +22,12 @@
 // entries; per lane the MAC r_c^2 <= theta^2 R^2 with the box farther than the near radius (computed in
 // FP64 without contraction, the same arithmetic as the oracle) decides between the proxy sum (original
 // kernels) and descending; at a leaf the remaining lanes sum the leaf's points directly, skipping the
-// near pairs (same pair_r2 test as the near-field kernel).  Output: one partial sum per channel and
-// target (the layout of the direct far field with a single split).
+// near pairs (same pair_r2 test as the near-field kernel).  The walk is split over the clusters of a
+// cut of the tree (the frontier, at most kMaxFrontier clusters; blockIdx.y selects one): a split
+// first applies the MAC to the frontier node's ancestors, root first, exactly as the per-target walk
+// would, so every target accepts the same clusters as in one walk; the proxy sum of an accepted
+// ancestor is added by the first frontier node below it.  Output: per split, one partial sum per
+// channel and target (the layout of the direct far field).
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -128,6 +132,41 @@ void build_tree(const double *hx, int64_t n, int64_t leaf, int p, TreeHost &T)
         if (nd.first_child < 0) nd.nchild = 0;
     }
     T.depth = depth_max;
+    // frontier: the tree cut level by level while it has at most kMaxFrontier nodes
+    std::vector<int> parent(T.nodes.size(), -1);
+    for (size_t id = 0; id < T.nodes.size(); ++id)
+        for (int k = 0; k < T.nodes[id].nchild; ++k) parent[T.nodes[id].first_child + k] = (int)id;
+    std::vector<int> F{0};
+    // every expanded level adds at least one cluster (a split has >= 2 children), so at most
+    // kMaxFrontier - 1 levels: the ancestor chains fit kMaxFrontierDepth
+    for (int level = 0; level < kMaxFrontierDepth - 1; ++level) {
+        std::vector<int> nxt;
+        for (int id : F) {
+            if (T.nodes[id].nchild == 0)
+                nxt.push_back(id);
+            else
+                for (int k = 0; k < T.nodes[id].nchild; ++k) nxt.push_back(T.nodes[id].first_child + k);
+        }
+        if (nxt == F || (int)nxt.size() > kMaxFrontier) break;
+        F.swap(nxt);
+    }
+    T.front.clear();
+    std::vector<char> seen(T.nodes.size(), 0);
+    for (int f : F) {
+        FrontierRec r{};
+        r.node = f;
+        int chain[kMaxFrontierDepth], nc = 0;
+        for (int a = parent[f]; a >= 0; a = parent[a]) chain[nc++] = a;  // frontier depth <= log8(kMaxFrontier)
+        r.nanc = nc;
+        for (int j = 0; j < nc; ++j) {
+            r.anc[j] = chain[nc - 1 - j];  // root first
+            if (!seen[r.anc[j]]) {
+                seen[r.anc[j]] = 1;
+                r.first |= 1 << j;
+            }
+        }
+        T.front.push_back(r);
+    }
     // Chebyshev points of each cluster
     const int np1 = p + 1, nprox = np1 * np1 * np1;
     T.cosk.resize(np1);
@@ -394,11 +433,15 @@ template <typename T, bool SL, bool DL>
 __device__ __forceinline__ void proxy_sum(const ProxRec<T> *__restrict__ pr, int nprox, const Lane<T> &L,
                                           double acc[6])
 {
+    // the record of the next proxy is loaded while the current one is evaluated (the index is
+    // wavefront-uniform: scalar loads, whose latency a plain loop would expose every iteration)
+    ProxRec<T> nxt = pr[0];
     for (int k0 = 0; k0 < nprox; k0 += kPromote) {
         T a[6] = {0, 0, 0, 0, 0, 0};
         const int k1 = min(k0 + kPromote, nprox);
         for (int k = k0; k < k1; ++k) {
-            const ProxRec<T> s = pr[k];
+            const ProxRec<T> s = nxt;
+            nxt = pr[min(k + 1, nprox - 1)];
             const T dx = L.y[0] - s.x, dy = L.y[1] - s.y, dz = L.y[2] - s.z;
             const T r2 = fma_t(dz, dz, fma_t(dy, dy, dx * dx));
             const T ir = rsqrt_t(r2);
@@ -435,11 +478,13 @@ template <typename T, bool SL, bool DL>
 __device__ __forceinline__ void leaf_sum(const SrcRec<T> *__restrict__ src, int b0, int b1, const Lane<T> &L, T rc2,
                                          double acc[6])
 {
+    SrcRec<T> nxt = src[b0];
     for (int k0 = b0; k0 < b1; k0 += kPromote) {
         T a[6] = {0, 0, 0, 0, 0, 0};
         const int k1 = min(k0 + kPromote, b1);
         for (int k = k0; k < k1; ++k) {
-            const SrcRec<T> s = src[k];
+            const SrcRec<T> s = nxt;
+            nxt = src[min(k + 1, b1 - 1)];
             const T dx = L.y[0] - s.x, dy = L.y[1] - s.y, dz = L.y[2] - s.z;
             const T r2 = pair_r2(L.y[0], L.y[1], L.y[2], s.x, s.y, s.z);
             const T ir = r2 > rc2 ? rsqrt_t(r2) : (T)0;  // near pairs belong to the near-field kernel
@@ -472,8 +517,9 @@ template <typename T, bool SL, bool DL>
 __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__restrict__ nodes,
                                                           const ProxRec<T> *__restrict__ prox, int nprox,
                                                           const SrcRec<T> *__restrict__ trec,
-                                                          const int *__restrict__ order, EvalArgs a, double theta2,
-                                                          double rnear2, T rc2, int stack_cap,
+                                                          const int *__restrict__ order,
+                                                          const FrontierRec *__restrict__ front, EvalArgs a,
+                                                          double theta2, double rnear2, T rc2, int stack_cap,
                                                           double *__restrict__ part)
 {
     extern __shared__ int smem[];
@@ -498,10 +544,22 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
              : (T)0;
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
+    // this split's frontier node: first its ancestors (root first), as the per-target walk would
+    // visit them; a lane that accepts one is done in this split, and the accepted ancestor's proxy
+    // sum is added by the first frontier node below it only
+    const FrontierRec &fr = front[blockIdx.y];
     uint64_t live = __ballot(valid);
+    for (int j = 0; j < fr.nanc; ++j) {
+        const int aid = fr.anc[j];
+        const TreeNode an = nodes[aid];
+        const bool acc_here = ((live >> lane) & 1) && mac_accept(an, yd[0], yd[1], yd[2], theta2, rnear2);
+        const uint64_t am = __ballot(acc_here);
+        if (am && ((fr.first >> j) & 1) && acc_here) proxy_sum<T, SL, DL>(prox + (size_t)aid * nprox, nprox, L, acc);
+        live &= ~am;
+    }
     int sp = 0;
     if (lane == 0) {
-        stk_node[0] = 0;
+        stk_node[0] = fr.node;
         stk_mask[0] = (uint32_t)live;
         stk_mask[1] = (uint32_t)(live >> 32);
     }
@@ -540,12 +598,13 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
         }
     }
     if (valid) {
+        double *ps = part + (size_t)blockIdx.y * 6 * (size_t)m;
         if (SL)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) part[(size_t)c * m + t] = acc[c];
+            for (int c = 0; c < 3; ++c) ps[(size_t)c * m + t] = acc[c];
         if (DL)
 #pragma unroll
-            for (int c = 3; c < 6; ++c) part[(size_t)c * m + t] = acc[c];
+            for (int c = 3; c < 6; ++c) ps[(size_t)c * m + t] = acc[c];
     }
 }
 
@@ -556,8 +615,8 @@ hipError_t launch_far_t(const TreeDev &D, const ProxRec<T> *prox, const SrcRec<T
     const int m = (int)a.m;
     const int blocks = (m + kBlock - 1) / kBlock;
     const size_t shmem = (size_t)(kBlock / kWave) * D.stack_cap * 3 * sizeof(int);
-    hipLaunchKernelGGL((tree_far_kernel<T, SL, DL>), dim3(blocks), dim3(kBlock), shmem, s, D.nodes, prox, D.nprox,
-                       trec, D.order, a, theta2, rnear2, rc2, D.stack_cap, part);
+    hipLaunchKernelGGL((tree_far_kernel<T, SL, DL>), dim3(blocks, D.nfront), dim3(kBlock), shmem, s, D.nodes, prox,
+                       D.nprox, trec, D.order, D.front, a, theta2, rnear2, rc2, D.stack_cap, part);
     return hipGetLastError();
 }
 

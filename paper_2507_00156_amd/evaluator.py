@@ -9,7 +9,7 @@ class Evaluator:
 
     def __init__(self, h: float, rho=(2.0, 3.0, 4.0), cutoff: float = 6.0, precision: int = B.SR_FP64,
                  far_method: int = B.SR_DIRECT, tree_degree: int = 8, tree_theta: float = 0.7,
-                 tree_leaf: int = 2000, device: int = 0):
+                 tree_leaf: int = 2000, surface_sharp: bool = False, sharp_rho: float = 3.0, device: int = 0):
         import torch
 
         self.device = torch.device("cuda", device)
@@ -24,6 +24,8 @@ class Evaluator:
         p.tree_degree = int(tree_degree)
         p.tree_theta = float(tree_theta)
         p.tree_leaf = int(tree_leaf)
+        p.surface_sharp = int(bool(surface_sharp))
+        p.sharp_rho = float(sharp_rho)
         try:
             B.sr_set_params(self.ctx, p)
         except Exception:
@@ -83,7 +85,7 @@ class RigidSpheres:
 
     def __init__(self, h: float, rho=(2.0, 3.0, 4.0), cutoff: float = 6.0, precision: int = B.SR_FP64,
                  far_method: int = B.SR_DIRECT, tree_degree: int = 8, tree_theta: float = 0.7,
-                 tree_leaf: int = 2000, device: int = 0):
+                 tree_leaf: int = 2000, surface_sharp: bool = False, sharp_rho: float = 3.0, device: int = 0):
         self.r = B.sr_rigid_create(device)
         p = B.sr_default_params()
         p.h = float(h)
@@ -95,6 +97,8 @@ class RigidSpheres:
         p.tree_degree = int(tree_degree)
         p.tree_theta = float(tree_theta)
         p.tree_leaf = int(tree_leaf)
+        p.surface_sharp = int(bool(surface_sharp))
+        p.sharp_rho = float(sharp_rho)
         try:
             B.sr_rigid_set_params(self.r, p)
         except Exception:
