@@ -44,6 +44,28 @@ FAR_FLOPS_PER_PAIR_SLDL = 57
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 
+# HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
+# for the kernel source it was measured on: reported as null once the source's hash differs.
+FAR_TRAFFIC = {"bytes": 7.649e7,
+               "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
+                           "d95c67bea2becca5ec78c295215d2eefd9c1f082cf6c66943a5391f4264b5578",
+                           "paper_2507_00156_amd/csrc/sr_internal.h":
+                           "75c560a1bb2d16224a4b55cef54e19f8f55f8e2d2393af19126d242b43f32dbe"}}
+
+
+def far_traffic():
+    import hashlib
+
+    for rel, digest in FAR_TRAFFIC["sources"].items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return FAR_TRAFFIC["bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -446,7 +468,8 @@ def main():
             "peak": PEAK_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": far_traffic() if a.precision == "mixed" else None,
+            "traffic_unit": "bytes per launch (HBM, counters scaled by a copy calibration)",
             "flops_per_pair": FAR_FLOPS_PER_PAIR_SLDL,
             "pairs_per_launch": M * N,
             "kernel_ms": far_ms,

@@ -270,12 +270,20 @@ __global__ __launch_bounds__(256) void loss_kernel(int B, int Bp, int64_t P, con
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void loss_final_kernel(const double *__restrict__ partial, int nb, double inv_count, double *__restrict__ out)
+// one block of 256: each thread sums a fixed strided subset, then a fixed-order tree (reproducible)
+__global__ __launch_bounds__(256) void loss_final_kernel(const double *__restrict__ partial, int nb, double inv_count,
+                                                         double *__restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[256];
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[b];
-    out[0] = s * inv_count;
+    for (int b = (int)threadIdx.x; b < nb; b += 256) s += partial[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] * inv_count;
 }
 
 // d = dh (1 - h^2)
@@ -295,6 +303,7 @@ __global__ __launch_bounds__(256) void colsum_kernel(int R, int N, const float *
     const int c = (int)(blockIdx.x * 256 + threadIdx.x);
     if (c >= N) return;
     float s = 0.f;
+#pragma unroll 8
     for (int r = 0; r < R; ++r) s += X[(int64_t)r * ldx + c];
     out[c] = s;
 }
@@ -307,6 +316,7 @@ __global__ __launch_bounds__(256) void l1_back_kernel(int B, int W, const float 
     const int w = (int)(blockIdx.x * 256 + threadIdx.x);
     if (w >= W) return;
     float a = 0.f, b = 0.f;
+#pragma unroll 8
     for (int n = 0; n < B; ++n) {
         const float d = d1[(int64_t)n * W + w];
         a = fmaf(d, gt[n], a);
@@ -515,8 +525,8 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
     hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, B, Bp, P, idx, y, P, M->scale, M->o, Pp, M->dout,
                        Pp, M->lpart);
     MHIP(hipGetLastError());
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, M->lpart, kLossBlocks, 1.0 / ((double)B * (double)P),
-                       M->lval);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, M->lpart, kLossBlocks,
+                       1.0 / ((double)B * (double)P), M->lval);
     MHIP(hipGetLastError());
     MSR(convert(M->dout, Bp, P, Pp, Bp, Pp, M->bdout, true, true, s));
     // head: dWh = dout^T z, dz = dout Wh
