@@ -23,6 +23,8 @@ import numpy as np
 
 from . import dl as _dl
 from . import dl_sharp as _dl_sharp
+from . import sl as _sl
+from . import sl_sharp as _sl_sharp
 
 PI = np.pi
 THETA = np.deg2rad(70.0)
@@ -106,10 +108,15 @@ def _lagrange(s, wdt):
 class RigidProblem:
     """Targets = all quadrature points of all spheres, in sphere order."""
 
-    def __init__(self, spheres, h, rho=(2.0, 3.0, 4.0), full=True, sharp=False, sharp_rho=3.0):
+    def __init__(self, spheres, h, rho=(2.0, 3.0, 4.0), full=True, sharp=False, sharp_rho=3.0, a_id=-0.5, a_dl=1.0,
+                 completion=True):
         self.S = spheres
         self.h = h
         self.rho = tuple(rho)
+        # the operator a_id q + a_dl sum_m DL_m[q] (+ the completion): -1/2, 1, on for the rigid-motion
+        # problem; lambda + 1, -2 (lambda - 1), off for the drops of section 4.3 (eq. (IE-2Surf) with the
+        # 1/(4 pi) integrals written as twice the 1/(8 pi) layers)
+        self.a_id, self.a_dl, self.completion_on = float(a_id), float(a_dl), bool(completion)
         # sharp: a sphere's own points (on its surface) use the modified smoothing at sharp_rho h
         # (paper section 2.1) instead of the extrapolation
         self.sharp, self.sharp_rho = bool(sharp), float(sharp_rho)
@@ -178,14 +185,36 @@ class RigidProblem:
 
     def matvec(self, q):
         q = np.asarray(q, float).reshape(self.ntot, 3)
-        return -0.5 * q + self.double_layers(q) + self.completion(q, self.y)
+        out = self.a_id * q + self.a_dl * self.double_layers(q)
+        return out + self.completion(q, self.y) if self.completion_on else out
+
+    def single_layers(self, f):
+        """sum_m SL_m[f_m] at every point: own points on the surface (the modified smoothing if sharp,
+        else the extrapolation with b = 0), other points nearly singular with f(x0) interpolated by the
+        same stencils as q(x0)."""
+        f = np.asarray(f, float).reshape(self.ntot, 3)
+        out = np.zeros((self.ntot, 3))
+        for s, fm, cr in zip(self.S, self.split(f), self.cross):
+            f0 = np.empty((self.ntot, 3))
+            f0[cr["own"]] = fm
+            f0[~cr["own"]] = np.einsum("ks,ksc->kc", cr["wts"], fm[cr["idx"]])
+            own = cr["own"]
+            if self.sharp:
+                out[own] += _sl_sharp(s.x, s.n, s.w, fm, self.y[own], cr["n0"][own], f0[own], self.sharp_rho * self.h)
+            else:
+                out[own] += _sl(s.x, s.n, s.w, fm, self.y[own], cr["x0"][own], cr["n0"][own], cr["b"][own], f0[own],
+                                self.h, self.rho)
+            out[~own] += _sl(s.x, s.n, s.w, fm, self.y[~own], cr["x0"][~own], cr["n0"][~own], cr["b"][~own],
+                             f0[~own], self.h, self.rho)
+        return out
 
     def matvec_rows(self, q, rows):
         """(A q) at the target rows only (the same arithmetic as matvec, restricted)."""
         q = np.asarray(q, float).reshape(self.ntot, 3)
         rows = np.asarray(rows)
         y = self.y[rows]
-        out = -0.5 * q[rows] + self.completion(q, y)
+        out = self.a_id * q[rows] + (self.completion(q, y) if self.completion_on else 0.0)
+        dls = np.zeros((len(rows), 3))
         for m, (s, qm) in enumerate(zip(self.S, self.split(q))):
             own = (rows >= self.off[m]) & (rows < self.off[m + 1])
             x0, n0, b = s.closest(y)
@@ -197,8 +226,8 @@ class RigidProblem:
             if (~own).any():
                 idx, wts = s.stencils(x0[~own])
                 q0[~own] = np.einsum("ks,ksc->kc", wts, qm[idx])
-            out += self._layer(s, qm, y, x0, n0, b, q0, own)
-        return out
+            dls += self._layer(s, qm, y, x0, n0, b, q0, own)
+        return out + self.a_dl * dls
 
     def velocity(self, q, y):
         """Exterior flow at points y outside every sphere: sum_m DL_m (chi = 0) + completion."""

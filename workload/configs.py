@@ -83,3 +83,28 @@ def two_spheres(h: float, gap: float, radius: float = 1.0):
 def rigid_motion(rng: np.random.Generator, nsph: int = 2) -> np.ndarray:
     """(nsph, 6) translation and rotation per sphere, N(0, 1)."""
     return rng.standard_normal((nsph, 6))
+
+
+def two_drops(h: float, eps: float = 1.0 / 16 ** 3):
+    """Two unit spheres centred at (0,0,0) and (2, 0, eps) (paper section 4.3; gap sqrt(4 + eps^2) - 2),
+    each with the grid-line quadrature in its own frame.  Returns (centers (2,3), radii, [s1, s2])."""
+    c1 = (0.0, 0.0, 0.0)
+    c2 = (2.0, 0.0, float(eps))
+    s1 = ellipsoid_quadrature((1.0, 1.0, 1.0), h, c1)
+    s2 = ellipsoid_quadrature((1.0, 1.0, 1.0), h, c2)
+    return np.array([c1, c2]), np.array([1.0, 1.0]), [s1, s2]
+
+
+def drop_force(x: np.ndarray, center) -> np.ndarray:
+    """Jump in surface force on a unit sphere with surface tension gamma = 1 + (x1 - c1)^2 (section 4.3):
+    [f] = 2 gamma H n - grad_S gamma with mean curvature H = 1 and n the outward normal;
+    grad_S gamma = (I - n n^T) grad gamma, grad gamma = (2 (x1 - c1), 0, 0)."""
+    x = np.asarray(x, float)
+    c = np.asarray(center, float)
+    d = x - c
+    n = d / np.linalg.norm(d, axis=1)[:, None]
+    gam = 1.0 + d[:, 0] ** 2
+    grad = np.zeros_like(x)
+    grad[:, 0] = 2.0 * d[:, 0]
+    grad_s = grad - n * (n * grad).sum(1)[:, None]
+    return 2.0 * gam[:, None] * n - grad_s
