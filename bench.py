@@ -19,6 +19,12 @@ Other workloads (--workload; each prints its own JSON line):
              a training step by phase, and of one inference.
   warmstart  the learned warm start end to end: solves at h = 1/64 kept at the h = 1/32 points train
              the network; held-out (gap, motion) pairs are solved from zero and from the prediction.
+  table1     the paper's Table 1 workload: prolate spheroid x1^2 + 4 x2^2 + 4 x3^2 = 1, grid targets
+             within h outside, single layer, rho = (3, 4, 5), h = 1/32 ... 1/256, direct far field.
+  sweep      treecode parameters (theta, leaf size N0, degree p) at the h = 1/128 spheroid: time and
+             error against the FP64 direct sum.
+  drops      the paper's two drops nearly touching (section 4.3): GMRES to 1e-10 at h = 1/16 ... 1/128,
+             iterations, times and the self-convergence errors of Table 2.
 """
 from __future__ import annotations
 
@@ -75,7 +81,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle baseline")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--workload", choices=["c2", "tree", "gmres", "mlp", "warmstart"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "tree", "gmres", "mlp", "warmstart", "table1", "sweep", "drops"],
+                    default="c2")
+    ap.add_argument("--drops-max", type=int, default=128, help="drops: finest 1/h")
     ap.add_argument("--train-solves", type=int, default=800, help="warmstart: training solves")
     ap.add_argument("--train-steps", type=int, default=60000, help="warmstart: optimizer steps")
     ap.add_argument("--heldout", type=int, default=60, help="warmstart: held-out solves")
@@ -246,6 +254,21 @@ def bench_gmres(a):
         per_gap[str(gap)] = {"seconds": dt, "inner_iterations": it, "fp64_corrections": nout, "fp64_relres": rr}
         log(f"[bench gmres] gap {gap}: {dt:.2f} s, {it} inner iterations, {nout} passes, residual {rr:.1e}")
         sysm.close()
+    # the same operator with the on-surface modified smoothing for each sphere's own points
+    sysm = W.TwoSpheres(h, 0.1, precision=1, surface_sharp=True)
+    q = sysm.R.rhs(workload.rigid_motion(np.random.default_rng(100)))
+    for _ in range(2):
+        sysm.R.matvec(q)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(max(3, a.steps // 4)):
+        sysm.R.matvec(q)
+    e1.record()
+    torch.cuda.synchronize()
+    mv_sharp_ms = e0.elapsed_time(e1) / max(3, a.steps // 4)
+    log(f"[bench gmres] matvec mixed {mv_ms:.2f} ms; with on-surface modified smoothing {mv_sharp_ms:.2f} ms")
+    sysm.close()
     ntot, nsph = 136332, 68166
     mean_s = float(np.mean([v["seconds"] for v in per_gap.values()]))
     out = base_line("seconds per two-sphere GMRES solve to FP64 relative residual 1e-8", mean_s, "s", 3, 1,
@@ -257,6 +280,7 @@ def bench_gmres(a):
     out["per_gap"] = per_gap
     out["matvec_ms_mixed"] = mv_ms
     out["matvec_interactions_per_s"] = 2 * nsph * ntot / (mv_ms / 1e3)
+    out["matvec_ms_mixed_surface_sharp"] = mv_sharp_ms
     print(json.dumps(out), flush=True)
 
 
@@ -393,6 +417,157 @@ def bench_warmstart(a):
     net.close()
 
 
+def _sl_setup(P, cfg, **kw):
+    import torch
+
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()  # noqa: E731
+    s, t = cfg["surf"], cfg["targets"]
+    ev = P.Evaluator(cfg["h"], cfg["rho"], **kw)
+    ev.set_surface(dev(s.x), dev(s.normal), dev(s.w))
+    ev.set_density(P.SR_SL, dev(cfg["f"]))
+    args = [dev(t.y), dev(t.x0), dev(t.n0), dev(t.b), dev(cfg["f0"]), None]
+    return ev, args
+
+
+def _time_sl(P, ev, args, steps):
+    import torch
+
+    (u,) = [ev.eval(P.SR_SL, *args)[0]]
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ev.eval(P.SR_SL, *args, out=(u, None, None, None))
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, u
+
+
+def bench_table1(a):
+    """The paper's Table 1 workload (single layer near the prolate spheroid) on the GPU."""
+    import paper_2507_00156_amd as P
+    import workload
+
+    paper_4thread_s = {32: 1.0, 64: 11.0, 128: 155.0, 256: 2461.0}
+    rows = {}
+    for inv_h in (32, 64, 128, 256):
+        log(f"[bench table1] generating the spheroid workload at h=1/{inv_h}")
+        cfg = workload.build_config("table1", h=1 / inv_h)
+        N, M = cfg["surf"].n, cfg["targets"].m
+        r = {"n_quads": N, "n_targets": M}
+        for name, prec in (("mixed", P.SR_MIXED), ("fp64", P.SR_FP64)):
+            ev, args = _sl_setup(P, cfg, precision=prec)
+            ms, u = _time_sl(P, ev, args, max(2, a.steps // (1 if inv_h < 256 else 4)))
+            r[name + "_ms"] = ms
+            r[name + "_pairs_per_s"] = M * N / (ms / 1e3)
+            if name == "fp64":
+                ref = u.clone()
+            else:
+                um = u.clone()
+            ev.close()
+        r["mixed_vs_fp64"] = ((um - ref).norm(dim=1).max() / ref.norm(dim=1).max()).item()
+        r["paper_4thread_cpu_s"] = paper_4thread_s[inv_h]
+        r["speedup_vs_paper_4thread_fp64"] = paper_4thread_s[inv_h] / (r["fp64_ms"] / 1e3)
+        rows[str(inv_h)] = r
+        log(f"[bench table1] h=1/{inv_h}: N={N} M={M} mixed {r['mixed_ms']:.2f} ms, fp64 {r['fp64_ms']:.2f} ms, "
+            f"mixed vs fp64 {r['mixed_vs_fp64']:.1e}")
+    top = rows["256"]
+    out = base_line("target-source interactions/s (extrapolated single layer, Table 1 workload h=1/256)",
+                    top["n_quads"] * top["n_targets"] / (top["mixed_ms"] / 1e3), "interactions/s", max(2, a.steps // 4),
+                    1, top["mixed_ms"], True, "f32+f64",
+                    "synthetic (the paper's spheroid and grid targets; density f1 = 1/sqrt(1 - 3 x1^2/4))",
+                    {"workload": "prolate spheroid x1^2+4x2^2+4x3^2=1, targets = grid points within h outside, single "
+                                 "layer, rho=(3,4,5), cutoff 6, direct far field; h = 1/32 .. 1/256"})
+    out["roofline"] = None
+    out["per_h"] = rows
+    out["note"] = "paper times: 4-thread Intel Core i7 2.3 GHz, FP64, context only"
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(a):
+    """Treecode parameter sweeps on the h = 1/128 spheroid (the paper's treecode study)."""
+    import paper_2507_00156_amd as P
+    import workload
+
+    cfg = workload.build_config("table1", h=1 / 128)
+    N, M = cfg["surf"].n, cfg["targets"].m
+    ev, args = _sl_setup(P, cfg, precision=P.SR_FP64)
+    ref_ms, ref = _time_sl(P, ev, args, 2)
+    ref = ref.clone()
+    ev.close()
+    ev, args = _sl_setup(P, cfg, precision=P.SR_MIXED)
+    dmix_ms, _ = _time_sl(P, ev, args, 3)
+    ev.close()
+    base = dict(theta=0.6, leaf=2000, p=8)
+    grid = [dict(base, theta=th) for th in (0.4, 0.5, 0.6, 0.7, 0.8)]
+    grid += [dict(base, leaf=n0) for n0 in (500, 1000, 4000, 8000, 16000)]
+    grid += [dict(base, p=p) for p in (4, 6, 10, 12)]
+    res = []
+    for g in grid:
+        ev, args = _sl_setup(P, cfg, precision=P.SR_MIXED, far_method=P.SR_TREE, tree_degree=g["p"],
+                             tree_theta=g["theta"], tree_leaf=g["leaf"])
+        ev.eval(P.SR_SL, *args)  # tree set-up and modified weights
+        ms, u = _time_sl(P, ev, args, 3)
+        err = ((u - ref).norm(dim=1).max() / ref.norm(dim=1).max()).item()
+        res.append(dict(g, ms=ms, err=err))
+        log(f"[bench sweep] theta {g['theta']} N0 {g['leaf']} p {g['p']}: {ms:.2f} ms, error {err:.2e}")
+        ev.close()
+    out = base_line("treecode parameter sweep (single layer, spheroid h=1/128): time and error vs FP64 direct",
+                    float(min(r["ms"] for r in res)), "ms", 3, 1, float(min(r["ms"] for r in res)), False, "f32+f64",
+                    "synthetic (the paper's spheroid, grid targets within h)",
+                    {"workload": f"prolate spheroid h=1/128 (N={N}, M={M}), single layer, rho=(3,4,5); sweeps of "
+                                 "theta, N0, p around theta 0.6, N0 2000, p 8"})
+    out["roofline"] = None
+    out["direct_fp64_ms"] = ref_ms
+    out["direct_mixed_ms"] = dmix_ms
+    out["sweep"] = res
+    print(json.dumps(out), flush=True)
+
+
+def bench_drops(a):
+    """Two drops nearly touching (eq. (IE-2Surf)): FP64 GMRES from zero to 1e-10, Table 2's columns."""
+    import torch
+
+    from paper_2507_00156_amd import drops
+
+    paper = {16: (13, 3.17e-3, 1.19e-4), 32: (12, 1.07e-4, 6.11e-6), 64: (12, 4.06e-6, 2.11e-7),
+             128: (12, 1.02e-7, 6.37e-9), 256: (12, None, None)}
+    levels = [n for n in (16, 32, 64, 128, 256) if n <= a.drops_max]
+    us, rows = {}, {}
+    for inv_h in levels:
+        T = drops.TwoDrops(1 / inv_h, precision=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, it, rr = T.solve(tol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        us[inv_h] = u.cpu().numpy()
+        rows[str(inv_h)] = {"n_points": int(sum(T.counts)), "iterations": it, "relres": rr, "seconds": dt,
+                            "paper_iterations": paper[inv_h][0]}
+        log(f"[bench drops] h=1/{inv_h}: {sum(T.counts)} points, {it} iterations (paper {paper[inv_h][0]}), "
+            f"relres {rr:.1e}, {dt:.2f} s")
+        T.close()
+    prev = None
+    for inv_h in levels[:-1]:
+        emax, el2 = drops.self_convergence(us[inv_h], us[2 * inv_h], 1 / inv_h)
+        r = rows[str(inv_h)]
+        r.update(max_err=emax, l2_err=el2, paper_max_err=paper[inv_h][1], paper_l2_err=paper[inv_h][2])
+        if prev is not None:
+            r["max_order"] = float(np.log2(prev[0] / emax))
+            r["l2_order"] = float(np.log2(prev[1] / el2))
+        prev = (emax, el2)
+        log(f"[bench drops] e_{inv_h}: max {emax:.3e} (paper {paper[inv_h][1]}), L2 {el2:.3e} (paper {paper[inv_h][2]})")
+    fin = rows[str(levels[-1])]
+    out = base_line("seconds per two-drop GMRES solve to relative residual 1e-10 (FP64)", fin["seconds"], "s", 1, 0,
+                    fin["seconds"] * 1e3, False, "f64",
+                    "synthetic (the paper's two drops: unit spheres at 0 and (2,0,1/16^3), surface tension 1+(x1-xc)^2)",
+                    {"workload": f"two drops nearly touching, lambda=2, h=1/16..1/{levels[-1]}, own-surface modified "
+                                 "smoothing delta=3h, cross-surface extrapolation delta=3h,4h,5h, direct far field"})
+    out["roofline"] = None
+    out["per_h"] = rows
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -409,7 +584,8 @@ def main():
         import paper_2507_00156_amd as P
 
         P.load_library()
-        {"tree": bench_tree, "gmres": bench_gmres, "mlp": bench_mlp, "warmstart": bench_warmstart}[a.workload](a)
+        {"tree": bench_tree, "gmres": bench_gmres, "mlp": bench_mlp, "warmstart": bench_warmstart,
+         "table1": bench_table1, "sweep": bench_sweep, "drops": bench_drops}[a.workload](a)
         return
     import torch
 

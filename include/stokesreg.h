@@ -162,6 +162,13 @@ sr_status sr_rigid_set_spheres(sr_rigid *r, int nsph, const double *centers, con
 sr_status sr_rigid_rhs(sr_rigid *r, const double *motion, double *rhs, void *stream);
 /* out = A q (device arrays (ntot,3)). */
 sr_status sr_rigid_matvec(sr_rigid *r, const double *q, double *out, void *stream);
+/* Replace the operator by A q = a_id q + a_dl sum_m DL_m[q] (+ the completion terms if completion != 0).
+ * Default: -1/2, 1, 1 (rigid spheres).  The drops of paper section 4.3 (eq. (IE-2Surf), viscosity
+ * ratio lambda, 1/(4 pi) integrals = twice the layers here) use lambda + 1, -2 (lambda - 1), 0. */
+sr_status sr_rigid_set_operator(sr_rigid *r, double a_id, double a_dl, int completion);
+/* out (ntot,3) = sum_m SL_m[f_m] at every point (f (ntot,3), device): own points on the surface, other
+ * points nearly singular with f(x0) interpolated by the same stencils as q(x0). */
+sr_status sr_rigid_single_layer(sr_rigid *r, const double *f, double *out, void *stream);
 /* Solve A x = rhs by restarted GMRES (device arrays).  x_is_guess != 0: x holds the initial guess,
  * else the iteration starts from 0.  Stops when the relative residual estimate |rhs - A x| / |rhs|
  * <= tol or after maxit matrix-vector products.  *iters = Arnoldi matrix-vector products;

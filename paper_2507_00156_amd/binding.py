@@ -23,7 +23,7 @@ _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
            "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy",
            "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
-           "sr_rigid_solve_refined", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
+           "sr_rigid_solve_refined", "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
            "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
            "sr_mlp_set_options", "sr_mlp_set_params", "sr_mlp_get_params", "sr_mlp_set_output_scale",
            "sr_mlp_fit_output_scale", "sr_mlp_get_output_scale", "sr_mlp_forward", "sr_mlp_predict",
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                  C.POINTER(C.c_double), vp]
     L.sr_rigid_solve_refined.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int,
                                          C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double), vp]
+    L.sr_rigid_set_operator.argtypes = [vp, C.c_double, C.c_double, C.c_int]
+    L.sr_rigid_single_layer.argtypes = [vp, vp, vp, vp]
     L.sr_rigid_velocity.argtypes = [vp, vp, i64, vp, vp, vp]
     L.sr_rigid_last_error.argtypes = []
     L.sr_rigid_last_error.restype = C.c_char_p
@@ -116,7 +118,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
                "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy", "sr_rigid_set_params",
                "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_solve_refined",
-               "sr_rigid_velocity"):
+               "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity"):
         getattr(L, fn).restype = C.c_int
     _lib = L
     return L
@@ -279,6 +281,16 @@ def sr_rigid_solve_refined(r, rhs, x, x_is_guess=False, tol=1e-10, inner_tol=1e-
                                                C.byref(no), C.byref(rr), _stream(stream))
     _rcheck("sr_rigid_solve_refined", st)
     return int(it.value), int(no.value), float(rr.value)
+
+
+def sr_rigid_set_operator(r, a_id: float, a_dl: float, completion: bool) -> None:
+    _rcheck("sr_rigid_set_operator", load_library().sr_rigid_set_operator(r, float(a_id), float(a_dl),
+                                                                          int(bool(completion))))
+
+
+def sr_rigid_single_layer(r, f, out, stream=None) -> None:
+    _rcheck("sr_rigid_single_layer", load_library().sr_rigid_single_layer(r, _ptr(f, "f", 3), _ptr(out, "out", 3),
+                                                                          _stream(stream)))
 
 
 def sr_rigid_velocity(r, q, y, u, stream=None) -> None:

@@ -154,19 +154,22 @@ __global__ void strengths_final_kernel(const double *__restrict__ part, int nsph
 }
 
 // out = [-1/2 q] + sum_m v_m + sum_m C_m(y), FL[m] = (F_m, L_m)
+// out = a_id q + a_dl sum_m v_m (+ the completion terms when `completion`)
 __global__ void assemble_kernel(const double *__restrict__ q, const double *__restrict__ y, int64_t nt, int nsph,
                                 const double *__restrict__ v, const double *__restrict__ centers,
-                                const double *__restrict__ FLs, double *__restrict__ out, int with_jump)
+                                const double *__restrict__ FLs, double *__restrict__ out, double a_id, double a_dl,
+                                int completion)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     double o[3] = {0.0, 0.0, 0.0};
-    if (with_jump) {
-        for (int c = 0; c < 3; ++c) o[c] = -0.5 * q[3 * t + c];
+    if (a_id != 0.0) {
+        for (int c = 0; c < 3; ++c) o[c] = a_id * q[3 * t + c];
     }
     const double k = 1.0 / (8.0 * kPi);
     for (int m = 0; m < nsph; ++m) {
-        for (int c = 0; c < 3; ++c) o[c] += v[((size_t)m * nt + t) * 3 + c];
+        for (int c = 0; c < 3; ++c) o[c] += a_dl * v[((size_t)m * nt + t) * 3 + c];
+        if (!completion) continue;
         const double *FL = FLs + 6 * m;
         const double dx = y[3 * t] - centers[3 * m], dy = y[3 * t + 1] - centers[3 * m + 1],
                      dz = y[3 * t + 2] - centers[3 * m + 2];
@@ -389,6 +392,9 @@ struct sr_rigid {
     // GMRES work
     Buf<double> V, wv, tmp, red, coef, r;
     Buf<double> rr, dd;                    // refined solve: outer residual and correction
+    // operator a_id q + a_dl sum_m DL_m[q] (+ completion): -1/2, 1, on for rigid spheres
+    double a_id = -0.5, a_dl = 1.0;
+    bool completion = true;
     bool ready = false;
 };
 
@@ -408,16 +414,20 @@ sr_status rigid_matvec(sr_rigid *R, const std::vector<sr_ctx *> &ctx, const doub
         RSR(sr_set_density(ctx[m], SR_DL, q + 3 * o, s));
         RSR(sr_eval(ctx[m], SR_DL, N, R->x.p, R->x0[m].p, R->n0[m].p, R->b[m].p, nullptr, R->q0[m].p, nullptr,
                     R->vall.p + (size_t)m * N * 3, nullptr, nullptr, s));
-        hipLaunchKernelGGL(strengths_kernel, dim3(kRedBlocks), dim3(kRed), 0, s, q, R->x.p, R->w.p, o, nm,
-                           R->centers[3 * m], R->centers[3 * m + 1], R->centers[3 * m + 2],
-                           R->part.p + (size_t)m * kRedBlocks * 6);
+        if (R->completion) {
+            hipLaunchKernelGGL(strengths_kernel, dim3(kRedBlocks), dim3(kRed), 0, s, q, R->x.p, R->w.p, o, nm,
+                               R->centers[3 * m], R->centers[3 * m + 1], R->centers[3 * m + 2],
+                               R->part.p + (size_t)m * kRedBlocks * 6);
+            RHIP(hipGetLastError());
+        }
+    }
+    if (R->completion) {
+        hipLaunchKernelGGL(strengths_final_kernel, dim3(1), dim3(64 * ((6 * R->nsph + 63) / 64)), 0, s, R->part.p,
+                           R->nsph, kRedBlocks, R->FL.p);
         RHIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(strengths_final_kernel, dim3(1), dim3(64 * ((6 * R->nsph + 63) / 64)), 0, s, R->part.p,
-                       R->nsph, kRedBlocks, R->FL.p);
-    RHIP(hipGetLastError());
     hipLaunchKernelGGL(assemble_kernel, dim3(nblocks(N)), dim3(256), 0, s, q, R->x.p, N, R->nsph, R->vall.p,
-                       R->dcenters.p, R->FL.p, out, 1);
+                       R->dcenters.p, R->FL.p, out, R->a_id, R->a_dl, R->completion ? 1 : 0);
     RHIP(hipGetLastError());
     return SR_OK;
 }
@@ -608,6 +618,41 @@ sr_status sr_rigid_matvec(sr_rigid *R, const double *q, double *out, void *strea
     return rigid_matvec(R, R->ctx, q, out, (hipStream_t)stream);
 }
 
+sr_status sr_rigid_set_operator(sr_rigid *R, double a_id, double a_dl, int completion)
+{
+    g_rerr.clear();
+    if (!R) return rfail(SR_EINVAL, "sr_rigid_set_operator: NULL argument");
+    if (!std::isfinite(a_id) || !std::isfinite(a_dl)) return rfail(SR_EINVAL, "sr_rigid_set_operator: not finite");
+    R->a_id = a_id;
+    R->a_dl = a_dl;
+    R->completion = completion != 0;
+    return SR_OK;
+}
+
+sr_status sr_rigid_single_layer(sr_rigid *R, const double *f, double *out, void *stream)
+{
+    g_rerr.clear();
+    if (!R || !f || !out) return rfail(SR_EINVAL, "sr_rigid_single_layer: NULL argument");
+    if (!R->ready) return rfail(SR_ESTATE, "sr_rigid_single_layer: set the spheres first");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = R->ntot;
+    RHIP(R->vall.alloc((size_t)R->nsph * N * 3));
+    for (int m = 0; m < R->nsph; ++m) {
+        const int64_t o = R->off[m], nm = R->off[m + 1] - o;
+        // f(x0): the sphere's own values at its points, the stencil interpolation elsewhere
+        hipLaunchKernelGGL(gather_q0_kernel, dim3(nblocks(N)), dim3(256), 0, s, f, N, o, o + nm, o, R->sidx[m].p,
+                           R->swts[m].p, R->q0[m].p);
+        RHIP(hipGetLastError());
+        RSR(sr_set_density(R->ctx[m], SR_SL, f + 3 * o, s));
+        RSR(sr_eval(R->ctx[m], SR_SL, N, R->x.p, R->x0[m].p, R->n0[m].p, R->b[m].p, R->q0[m].p, nullptr,
+                    R->vall.p + (size_t)m * N * 3, nullptr, nullptr, nullptr, s));
+    }
+    hipLaunchKernelGGL(assemble_kernel, dim3(nblocks(N)), dim3(256), 0, s, f, R->x.p, N, R->nsph, R->vall.p,
+                       R->dcenters.p, R->FL.p, out, 0.0, 1.0, 0);
+    RHIP(hipGetLastError());
+    return SR_OK;
+}
+
 sr_status sr_rigid_velocity(sr_rigid *R, const double *q, int64_t m, const double *y, double *u, void *stream)
 {
     g_rerr.clear();
@@ -668,7 +713,7 @@ sr_status sr_rigid_velocity(sr_rigid *R, const double *q, int64_t m, const doubl
                        kRedBlocks, FL.p);
     RHIP(hipGetLastError());
     hipLaunchKernelGGL(assemble_kernel, dim3(nblocks(m)), dim3(256), 0, s, q, y, m, R->nsph, vv.p, R->dcenters.p,
-                       FL.p, u, 0);
+                       FL.p, u, 0.0, 1.0, 1);
     RHIP(hipGetLastError());
     RHIP(hipStreamSynchronize(s));  // temporaries die at return
     return SR_OK;

@@ -136,6 +136,16 @@ class RigidSpheres:
         B.sr_rigid_matvec(self.r, q, out, stream)
         return out
 
+    def set_operator(self, a_id: float, a_dl: float, completion: bool) -> None:
+        B.sr_rigid_set_operator(self.r, a_id, a_dl, completion)
+
+    def single_layer(self, f, stream=None):
+        import torch
+
+        out = torch.empty_like(f)
+        B.sr_rigid_single_layer(self.r, f, out, stream)
+        return out
+
     def solve(self, rhs, x0=None, tol=1e-8, maxit=200, restart=60, stream=None):
         """Returns (x, iterations, relative residual)."""
         import torch

@@ -30,7 +30,7 @@ def _dev(a):
 class TwoSpheres:
     """Two unit spheres at a gap: quadrature on the device and the library's rigid-motion operator."""
 
-    def __init__(self, h: float, gap: float, precision: int = 1, far_method: int = 0):
+    def __init__(self, h: float, gap: float, precision: int = 1, far_method: int = 0, **kw):
         self.h, self.gap = float(h), float(gap)
         self.centers, self.radii, surfs = workload.two_spheres(h, gap)
         self.counts = [s.n for s in surfs]
@@ -38,7 +38,7 @@ class TwoSpheres:
         self.nrm = _dev(np.concatenate([s.normal for s in surfs]))
         self.w = _dev(np.concatenate([s.w for s in surfs]))
         self.ntot = int(sum(self.counts))
-        self.R = RigidSpheres(h, precision=precision, far_method=far_method)
+        self.R = RigidSpheres(h, precision=precision, far_method=far_method, **kw)
         self.R.set_spheres(self.centers, self.radii, self.counts, self.x, self.nrm, self.w)
 
     def close(self):
