@@ -554,6 +554,7 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     dp.cutoff = c->prm.cutoff;
     dp.rnear = c->grid_rnear;
     dp.precision = c->prm.precision;
+    dp.pow234 = (2.0 * dp.rho[1] == 3.0 * dp.rho[0] && dp.rho[2] == 2.0 * dp.rho[0]) ? 1 : 0;
     dp.sharp = c->prm.surface_sharp ? 1 : 0;
     dp.inv_dsharp = 1.0 / (c->prm.sharp_rho * c->prm.h);
 

@@ -85,6 +85,7 @@ struct DevParams {
     double cutoff;       // in t = r / delta
     double rnear;        // cutoff * max_j delta_j (and the modified-smoothing delta if larger)
     int precision;
+    int pow234;          // the sorted deltas are in the ratio 2 : 3 : 4 (exp(-t_j^2) by powers of one exp)
     int sharp;           // targets on the surface (b == 0) use the modified smoothing at one delta
     double inv_dsharp;   // 1 / that delta
 };

@@ -89,15 +89,15 @@ constexpr SeriesCoef make_series()
 }
 __constant__ constexpr SeriesCoef kSeries = make_series();
 
-// s1, s2, s3 at t >= 0 (eqs. (s1)-(s3)), replaced by 1 for t > cutoff and by 0 for t < kSeriesT (the
+// s1, s2, s3 at t >= 0 (eqs. (s1)-(s3)) given E = exp(-t^2), replaced by 1 for t > cutoff and by 0 for
+// t < kSeriesT (the
 // pairs closer than kSeriesT delta are added separately by near_pair_series, whose Maclaurin series
 // keep the relative accuracy of s2 ~ t^3 and s3 ~ t^5 that the differences below would lose).
 // erfc(t) = exp(-t^2) erfcx(t), erfcx from the interpolating polynomial of sr_erfcx_table.h (|erfc
 // error| < 1e-15 on [0, 6.25]); beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
-__device__ __forceinline__ void smoothing3(double t, double cutoff, double &s1, double &s2, double &s3)
+__device__ __forceinline__ void smoothing3(double t, double E, double cutoff, double &s1, double &s2, double &s3)
 {
     using namespace erfcx_poly;
-    const double E = exp(-t * t);
     const double tc = fmin(t, 6.25);
     const double den = tc + kL;
     double inv = __builtin_amdgcn_rcp(den);
@@ -239,13 +239,13 @@ __device__ __forceinline__ void add_delta(double s1, double s2, double s3, doubl
 }
 
 template <int J, bool SL, bool DL>
-__device__ __forceinline__ void accumulate_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
-                                                 double dz, double gx, double gy, double gz, double dg, double t1x,
-                                                 double t1y, double t1z, double ex, double ey, double ez,
+__device__ __forceinline__ void accumulate_delta(double r, double E, double ir, double ir3, double ir5, double dx,
+                                                 double dy, double dz, double gx, double gy, double gz, double dg,
+                                                 double t1x, double t1y, double t1z, double ex, double ey, double ez,
                                                  const DevParams &p, Acc &A)
 {
     double s1, s2, s3;
-    smoothing3(r * p.inv_delta[J], p.cutoff, s1, s2, s3);
+    smoothing3(r * p.inv_delta[J], E, p.cutoff, s1, s2, s3);
     add_delta<J, SL, DL>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, A);
 }
 
@@ -268,7 +268,7 @@ __device__ __forceinline__ void series_delta(double r, double ir, double ir3, do
 // One near pair, accumulated at the three smoothing lengths (sorted-delta order).  SER = false: the
 // closed-form smoothing factors, leaving out t < kSeriesT; returns whether some t is below kSeriesT
 // (then the caller calls it again with SER = true, which adds just those terms from the series).
-template <bool SL, bool DL, bool SER>
+template <bool SL, bool DL, bool SER, bool P234>
 __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
 {
     const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
@@ -331,22 +331,49 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
         series_delta<2, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
         return false;
     }
-    accumulate_delta<0, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
-    accumulate_delta<1, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
-    accumulate_delta<2, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+    // e^{-t_j^2} for the three deltas.  P234 (sorted deltas in the ratio 2 : 3 : 4, the default rho):
+    // B^36, B^16, B^9 of B = e^{-(t_0/6)^2}, one exponential and seven products (relative error ~50
+    // ulp), taken in the order that keeps the fewest powers alive; otherwise three exponentials.
+    if (P234) {
+        const double tb = r * p.inv_delta[0] * (1.0 / 6.0);
+        const double B = exp(-tb * tb);
+        const double B4 = (B * B) * (B * B), B8 = B4 * B4;
+        accumulate_delta<2, SL, DL>(r, B8 * B, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
+                                    A);
+        const double B16 = B8 * B8;
+        accumulate_delta<1, SL, DL>(r, B16, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
+                                    A);
+        accumulate_delta<0, SL, DL>(r, (B16 * B16) * B4, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex,
+                                    ey, ez, p, A);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double tj = r * p.inv_delta[j];
+            const double Ej = exp(-tj * tj);
+            if (j == 0)
+                accumulate_delta<0, SL, DL>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                            p, A);
+            else if (j == 1)
+                accumulate_delta<1, SL, DL>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                            p, A);
+            else
+                accumulate_delta<2, SL, DL>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                            p, A);
+        }
+    }
     return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
 }
 
 // A near pair: the closed-form pass, then (rarely) the series pass.  The empty asm hides that the
 // second load reads the same record, so the record is not kept in registers across the first pass.
-template <bool SL, bool DL>
+template <bool SL, bool DL, bool P234>
 __device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
                                                const DevParams &p, Acc &A)
 {
-    if (near_pair<SL, DL, false>(rec64[k], T, p, A)) {
+    if (near_pair<SL, DL, false, P234>(rec64[k], T, p, A)) {
         int kk = k;
         asm volatile("" : "+v"(kk));
-        near_pair<SL, DL, true>(rec64[kk], T, p, A);
+        near_pair<SL, DL, true, P234>(rec64[kk], T, p, A);
     }
 }
 
@@ -417,8 +444,8 @@ __device__ __forceinline__ void near_pair_sharp_full(const SrcRec<double> *__res
     }
 }
 
-template <typename TC, bool SL, bool DL, bool SHARP>
-__global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
+template <typename TC, bool SL, bool DL, bool SHARP, bool P234>
+__global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
                                                                const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
                                                                EvalArgs a, DevParams p, TC rc2,
@@ -496,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
                     if (SHARP)
                         near_pair_sharp_full<SL, DL>(rec64, k2, T, p, A);
                     else
-                        near_pair_full<SL, DL>(rec64, k2, T, p, A);
+                        near_pair_full<SL, DL, P234>(rec64, k2, T, p, A);
                 }
             }
         }
@@ -506,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
         if (SHARP)
             near_pair_sharp_full<SL, DL>(rec64, queue[lane], T, p, A);
         else
-            near_pair_full<SL, DL>(rec64, queue[lane], T, p, A);
+            near_pair_full<SL, DL, P234>(rec64, queue[lane], T, p, A);
     }
 
 #pragma unroll
@@ -573,12 +600,16 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
 {
     const int per_block = kBlock / kWave;
     const int64_t blocks = (a.m + per_block - 1) / per_block;
-    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64,
-                       pos, cell_start, g, a, p, rc2, part, nparts);
+    if (p.pow234)
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           rec64, pos, cell_start, g, a, p, rc2, part, nparts);
+    else
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           rec64, pos, cell_start, g, a, p, rc2, part, nparts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.sharp) return e;
-    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, rec64,
-                       pos, cell_start, g, a, p, rc2, part, nparts);
+    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       rec64, pos, cell_start, g, a, p, rc2, part, nparts);
     return hipGetLastError();
 }
 
