@@ -53,11 +53,11 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 # HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
 # for the kernel source it was measured on: reported as null once the source's hash differs.
-FAR_TRAFFIC = {"bytes": 7.649e7,
+FAR_TRAFFIC = {"bytes": 7.657e7,
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "d95c67bea2becca5ec78c295215d2eefd9c1f082cf6c66943a5391f4264b5578",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "75c560a1bb2d16224a4b55cef54e19f8f55f8e2d2393af19126d242b43f32dbe"}}
+                           "e0b3578ad47e05aed2defd173252a37757c76cdfd81b10c4f108ee30b9e3ec1b"}}
 
 
 def far_traffic():
@@ -227,8 +227,22 @@ def bench_gmres(a):
     from paper_2507_00156_amd import warmstart as W
 
     h = 1 / 64
-    per_gap = {}
+    tree_kw = dict(far_method=1, tree_degree=6, tree_theta=0.6, tree_leaf=4000)
+    per_gap, per_gap_tree = {}, {}
     mv_ms = None
+    for gap in (0.1, 0.05, 0.02):
+        sysm = W.TwoSpheres(h, gap, precision=1, **tree_kw)
+        motion = workload.rigid_motion(np.random.default_rng(int(round(gap * 1000))))
+        b = sysm.R.rhs(motion)
+        sysm.R.solve_refined(b, tol=1e-8, restart=100)  # set-up (untimed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, nout, rr = sysm.R.solve_refined(b, tol=1e-8, restart=100)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        per_gap_tree[str(gap)] = {"seconds": dt, "inner_iterations": it, "fp64_corrections": nout, "fp64_relres": rr}
+        log(f"[bench gmres] treecode gap {gap}: {dt:.2f} s, {it} inner iterations, {nout} passes, residual {rr:.1e}")
+        sysm.close()
     for gap in (0.1, 0.05, 0.02):
         sysm = W.TwoSpheres(h, gap, precision=1)
         motion = workload.rigid_motion(np.random.default_rng(int(round(gap * 1000))))
@@ -270,14 +284,18 @@ def bench_gmres(a):
     log(f"[bench gmres] matvec mixed {mv_ms:.2f} ms; with on-surface modified smoothing {mv_sharp_ms:.2f} ms")
     sysm.close()
     ntot, nsph = 136332, 68166
-    mean_s = float(np.mean([v["seconds"] for v in per_gap.values()]))
+    mean_s = float(np.mean([v["seconds"] for v in per_gap_tree.values()]))
     out = base_line("seconds per two-sphere GMRES solve to FP64 relative residual 1e-8", mean_s, "s", 3, 1,
                     mean_s * 1e3, False, "f32+f64",
                     "synthetic (two unit spheres, grid-line quadrature, seeded random rigid motions)",
                     {"workload": "two unit spheres, h=1/64 (136332 points, 408996 unknowns), gaps 0.1/0.05/0.02, "
-                                 "completed double layer, mixed operator with FP64 refinement, restart 100"})
+                                 "completed double layer; inner operator mixed precision with the treecode far field "
+                                 "(degree 6, theta 0.6, leaf 4000), outer residuals FP64 with the direct far field; "
+                                 "restart 100"})
     out["roofline"] = None
-    out["per_gap"] = per_gap
+    out["per_gap"] = per_gap_tree
+    out["per_gap_direct_far_field"] = per_gap
+    out["seconds_direct_far_field_mean"] = float(np.mean([v["seconds"] for v in per_gap.values()]))
     out["matvec_ms_mixed"] = mv_ms
     out["matvec_interactions_per_s"] = 2 * nsph * ntot / (mv_ms / 1e3)
     out["matvec_ms_mixed_surface_sharp"] = mv_sharp_ms

@@ -177,8 +177,8 @@ sr_status sr_rigid_single_layer(sr_rigid *r, const double *f, double *out, void 
 sr_status sr_rigid_solve(sr_rigid *r, const double *rhs, double *x, int x_is_guess, double tol, int maxit,
                          int restart, int *iters, double *relres, void *stream);
 /* Solve A x = rhs by iterative refinement: outer residuals rhs - A x with the operator evaluated in
- * FP64 (SR_FP64 evaluators, built on the first call), corrections from restarted GMRES with the
- * parameters' precision, each reducing the residual by the factor max(inner_tol, tol |rhs| / (2 |r|))
+ * FP64 with the direct far field (SR_FP64, SR_DIRECT evaluators, built on the first call), corrections
+ * from restarted GMRES with the parameters' precision and far-field method, each reducing the residual by the factor max(inner_tol, tol |rhs| / (2 |r|))
  * (at most 0.5; 0 < inner_tol < 1, about 1e-6 suits SR_MIXED), so a pass stops once the outer
  * tolerance is within reach.  Use it
  * with SR_MIXED parameters when tol lies below the mixed operator's own error (about 1e-7 relative).
