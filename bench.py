@@ -53,7 +53,7 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 # HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
 # for the kernel source it was measured on: reported as null once the source's hash differs.
-FAR_TRAFFIC = {"bytes": 7.657e7,
+FAR_TRAFFIC = {"bytes": 7.710e7,
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "d95c67bea2becca5ec78c295215d2eefd9c1f082cf6c66943a5391f4264b5578",
                            "paper_2507_00156_amd/csrc/sr_internal.h":

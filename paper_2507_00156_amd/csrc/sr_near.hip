@@ -18,15 +18,18 @@
 //
 // Work decomposition: one wavefront per target (4 per workgroup).  The target's cell and its
 // neighbours in the uniform cell grid (side >= near radius) hold every near pair; with cells in
-// z-fastest order, the 27 neighbour cells are 9 contiguous ranges.  The 64 lanes test 64 candidates
-// at a time (compact single- or double-precision positions) and append the near ones to a per-wave
-// queue in LDS; each time the queue holds 64 pairs, all 64 lanes evaluate one pair each, so the
-// FP64 regularized kernels run without idle lanes.  The three smoothing factors of a pair share one
-// exp(-t^2) and one polynomial (no branches): s_k = 1 - exp(-t^2) P_k(t) with
-// P_1 = erfcx(t), P_2 = P_1 + (2/sqrt(pi)) t, P_3 = P_2 + (4/(3 sqrt(pi))) t^3.
-// Every pair evaluates all three smoothing lengths: sorting pairs into per-delta classes would skip
-// about 40% of the smoothing work, but the class-specialized code needs enough registers to halve
-// the wavefronts per SIMD, which costs more than it saves (measured on MI355X).
+// z-fastest order, the 27 neighbour cells are 9 contiguous ranges.  The 64 lanes test candidates 64 at
+// a time (compact single- or double-precision positions; several such loads in flight per wavefront)
+// and append the near ones to a per-wave ring buffer in LDS; each time it holds 64 pairs, all 64 lanes
+// evaluate one pair each, so the FP64 regularized kernels run without idle lanes.  The three smoothing
+// factors of a pair share one exp(-t^2) and one polynomial (no branches): s_k = 1 - exp(-t^2) P_k(t)
+// with P_1 = erfcx(t), P_2 = P_1 + (2/sqrt(pi)) t, P_3 = P_2 + (4/(3 sqrt(pi))) t^3.
+// When only the extrapolated values are asked for, the weights w_j are computed first and a pair
+// adds K(S), S_k = sum_j w_j s_k(t_j), to one set of accumulators (the kernels are linear in s_k).
+// Every pair evaluates all three smoothing lengths.  Skipping the lengths whose cut-off ball does not
+// hold the pair saves about 40% of the smoothing work, but it needs pairs sorted into per-class queues
+// so that a batch of 64 shares its class; measured on MI355X, the queue bookkeeping cost more than the
+// smoothing it saved (per-class queues: 27% fewer FP64 FMAs, 19% more VALU instructions in all).
 // Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
 #include <math.h>
 
@@ -34,6 +37,21 @@
 #include "sr_internal.h"
 
 namespace sr {
+
+// The erfcx coefficients as a device variable with external linkage: the compiler cannot fold them
+// into immediates, so the polynomial reads them with scalar loads into SGPRs instead of keeping 17
+// FP64 constants (34 VGPRs) live across the pair loop.
+struct ErfcxCoef {
+    double c[erfcx_poly::kDegree + 1];
+};
+constexpr ErfcxCoef make_erfcx_coef()
+{
+    ErfcxCoef r{};
+    for (int k = 0; k <= erfcx_poly::kDegree; ++k) r.c[k] = erfcx_poly::kC[k];
+    return r;
+}
+__constant__ ErfcxCoef g_erfcx_coef = make_erfcx_coef();
+
 namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
@@ -106,9 +124,9 @@ __device__ __forceinline__ void smoothing3(double t, double E, double cutoff, do
     e = __builtin_fma(-den, inv, 1.0);
     inv = __builtin_fma(inv, e, inv);
     const double x = __builtin_fma(kA, (tc - kL) * inv, kB);
-    double pz = kC[kDegree];
+    double pz = g_erfcx_coef.c[kDegree];
 #pragma unroll
-    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, kC[k]);
+    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef.c[k]);
     const double R = kL * inv * pz;
     const double P2 = __builtin_fma(kTwoOverSqrtPi, t, R);
     const double P3 = __builtin_fma((2.0 / 3.0) * kTwoOverSqrtPi * t * t, t, P2);
@@ -152,9 +170,9 @@ __device__ __forceinline__ void smoothing3_sharp(double t, double cutoff, double
     e = __builtin_fma(-den, inv, 1.0);
     inv = __builtin_fma(inv, e, inv);
     const double x = __builtin_fma(kA, (tc - kL) * inv, kB);
-    double pz = kC[kDegree];
+    double pz = g_erfcx_coef.c[kDegree];
 #pragma unroll
-    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, kC[k]);
+    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef.c[k]);
     const double R = kL * inv * pz;
     const double t2 = t * t, c3 = kTwoOverSqrtPi / 3.0, c9 = kTwoOverSqrtPi / 9.0;
     const double P1 = R - c3 * t * __builtin_fma(-2.0, t2, 5.0);
@@ -211,6 +229,7 @@ __device__ __forceinline__ double pick3(const double (&v)[3], int i) { return i 
 
 struct Target {
     double y[3], x0[3], n[3], b, c, q0[3];
+    double w[3];  // extrapolation weights (sorted-delta order), used when the sums are combined
 };
 
 struct Acc {
@@ -218,57 +237,67 @@ struct Acc {
 };
 
 // Adds one pair's contribution with smoothing factors s1, s2, s3 at sorted position J.
-template <int J, bool SL, bool DL>
+// COMB: the extrapolation weight w_J is applied here and every delta adds into slot 0 (one set of
+// accumulators: sum_j w_j (far + near_j) = far + sum_j w_j near_j since the weights sum to 1).
+template <int J, bool SL, bool DL, bool COMB>
 __device__ __forceinline__ void add_delta(double s1, double s2, double s3, double ir, double ir3, double ir5,
                                           double dx, double dy, double dz, double gx, double gy, double gz,
                                           double dg, double t1x, double t1y, double t1z, double ex, double ey,
-                                          double ez, Acc &A)
+                                          double ez, double wJ, Acc &A)
 {
+    constexpr int K = COMB ? 0 : J;
+    if (COMB) {
+        s1 *= wJ;
+        s2 *= wJ;
+        s3 *= wJ;
+    }
     if (SL) {
         const double k1 = s1 * ir, k2 = dg * s2 * ir3;
-        A.sl[J][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[J][0]));
-        A.sl[J][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[J][1]));
-        A.sl[J][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[J][2]));
+        A.sl[K][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[K][0]));
+        A.sl[K][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[K][1]));
+        A.sl[K][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[K][2]));
     }
     if (DL) {
         const double k2 = s2 * ir3, k3 = s3 * ir5;
-        A.dl[J][0] = __builtin_fma(ex, k3, __builtin_fma(t1x, k2, A.dl[J][0]));
-        A.dl[J][1] = __builtin_fma(ey, k3, __builtin_fma(t1y, k2, A.dl[J][1]));
-        A.dl[J][2] = __builtin_fma(ez, k3, __builtin_fma(t1z, k2, A.dl[J][2]));
+        A.dl[K][0] = __builtin_fma(ex, k3, __builtin_fma(t1x, k2, A.dl[K][0]));
+        A.dl[K][1] = __builtin_fma(ey, k3, __builtin_fma(t1y, k2, A.dl[K][1]));
+        A.dl[K][2] = __builtin_fma(ez, k3, __builtin_fma(t1z, k2, A.dl[K][2]));
     }
 }
 
-template <int J, bool SL, bool DL>
+template <int J, bool SL, bool DL, bool COMB>
 __device__ __forceinline__ void accumulate_delta(double r, double E, double ir, double ir3, double ir5, double dx,
                                                  double dy, double dz, double gx, double gy, double gz, double dg,
                                                  double t1x, double t1y, double t1z, double ex, double ey, double ez,
-                                                 const DevParams &p, Acc &A)
+                                                 const DevParams &p, const Target &T, Acc &A)
 {
     double s1, s2, s3;
     smoothing3(r * p.inv_delta[J], E, p.cutoff, s1, s2, s3);
-    add_delta<J, SL, DL>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, A);
+    add_delta<J, SL, DL, COMB>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                               T.w[J], A);
 }
 
 // The contributions that smoothing3 left out (t < kSeriesT), from the series.  Rarely executed: only
 // pairs closer than kSeriesT times the largest delta reach it.
-template <int J, bool SL, bool DL>
+template <int J, bool SL, bool DL, bool COMB>
 __device__ __forceinline__ void series_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
                                              double dz, double gx, double gy, double gz, double dg, double t1x,
                                              double t1y, double t1z, double ex, double ey, double ez,
-                                             const DevParams &p, Acc &A)
+                                             const DevParams &p, const Target &T, Acc &A)
 {
     const double t = r * p.inv_delta[J];
     if (t < kSeriesT) {
         double s1, s2, s3;
         series3(t, s1, s2, s3);
-        add_delta<J, SL, DL>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, A);
+        add_delta<J, SL, DL, COMB>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                   T.w[J], A);
     }
 }
 
 // One near pair, accumulated at the three smoothing lengths (sorted-delta order).  SER = false: the
 // closed-form smoothing factors, leaving out t < kSeriesT; returns whether some t is below kSeriesT
 // (then the caller calls it again with SER = true, which adds just those terms from the series).
-template <bool SL, bool DL, bool SER, bool P234>
+template <bool SL, bool DL, bool SER, bool P234, bool COMB>
 __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
 {
     const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
@@ -281,10 +310,11 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
             const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const double l = kTwoOverSqrtPi * p.inv_delta[j];
-                A.sl[j][0] += gx * l;
-                A.sl[j][1] += gy * l;
-                A.sl[j][2] += gz * l;
+                const double l = kTwoOverSqrtPi * p.inv_delta[j] * (COMB ? T.w[j] : 1.0);
+                const int k = COMB ? 0 : j;
+                A.sl[k][0] += gx * l;
+                A.sl[k][1] += gy * l;
+                A.sl[k][2] += gz * l;
             }
         }
         return false;
@@ -326,9 +356,9 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
         ez = hz * c2h + nz * c2n - rmb * t1z;
     }
     if (SER) {
-        series_delta<0, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
-        series_delta<1, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
-        series_delta<2, SL, DL>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, A);
+        series_delta<0, SL, DL, COMB>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, T, A);
+        series_delta<1, SL, DL, COMB>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, T, A);
+        series_delta<2, SL, DL, COMB>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, T, A);
         return false;
     }
     // e^{-t_j^2} for the three deltas.  P234 (sorted deltas in the ratio 2 : 3 : 4, the default rho):
@@ -338,27 +368,27 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
         const double tb = r * p.inv_delta[0] * (1.0 / 6.0);
         const double B = exp(-tb * tb);
         const double B4 = (B * B) * (B * B), B8 = B4 * B4;
-        accumulate_delta<2, SL, DL>(r, B8 * B, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
-                                    A);
+        accumulate_delta<2, SL, DL, COMB>(r, B8 * B, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
+                                    T, A);
         const double B16 = B8 * B8;
-        accumulate_delta<1, SL, DL>(r, B16, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
-                                    A);
-        accumulate_delta<0, SL, DL>(r, (B16 * B16) * B4, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex,
-                                    ey, ez, p, A);
+        accumulate_delta<1, SL, DL, COMB>(r, B16, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
+                                    T, A);
+        accumulate_delta<0, SL, DL, COMB>(r, (B16 * B16) * B4, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex,
+                                    ey, ez, p, T, A);
     } else {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const double tj = r * p.inv_delta[j];
             const double Ej = exp(-tj * tj);
             if (j == 0)
-                accumulate_delta<0, SL, DL>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                            p, A);
+                accumulate_delta<0, SL, DL, COMB>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                            p, T, A);
             else if (j == 1)
-                accumulate_delta<1, SL, DL>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                            p, A);
+                accumulate_delta<1, SL, DL, COMB>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                            p, T, A);
             else
-                accumulate_delta<2, SL, DL>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                            p, A);
+                accumulate_delta<2, SL, DL, COMB>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                                            p, T, A);
         }
     }
     return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
@@ -366,14 +396,120 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
 
 // A near pair: the closed-form pass, then (rarely) the series pass.  The empty asm hides that the
 // second load reads the same record, so the record is not kept in registers across the first pass.
-template <bool SL, bool DL, bool P234>
+template <bool SL, bool DL, bool P234, bool COMB>
 __device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
                                                const DevParams &p, Acc &A)
 {
-    if (near_pair<SL, DL, false, P234>(rec64[k], T, p, A)) {
+    if (near_pair<SL, DL, false, P234, COMB>(rec64[k], T, p, A)) {
         int kk = k;
         asm volatile("" : "+v"(kk));
-        near_pair<SL, DL, true, P234>(rec64[kk], T, p, A);
+        near_pair<SL, DL, true, P234, COMB>(rec64[kk], T, p, A);
+    }
+}
+
+// Combined closed-form pass (COMB): the kernels are linear in (s1, s2, s3), so
+// sum_j w_j K(s(t_j)) = K(S) with S_k = sum_j w_j s_k(t_j): the three smoothing lengths share one kernel
+// evaluation and one set of accumulators.  Returns whether t < kSeriesT for some delta (then the
+// series pass adds those terms).
+template <bool SL, bool DL, bool P234>
+__device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
+{
+    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 == 0.0) {
+        // target on a quadrature point: limit of s1(r/delta)/r is 2/(sqrt(pi) delta); the d d s2/r^3
+        // term and the whole double-layer term vanish
+        if (SL) {
+            const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
+            const double l = kTwoOverSqrtPi *
+                             (T.w[0] * p.inv_delta[0] + T.w[1] * p.inv_delta[1] + T.w[2] * p.inv_delta[2]);
+            A.sl[0][0] += gx * l;
+            A.sl[0][1] += gy * l;
+            A.sl[0][2] += gz * l;
+        }
+        return false;
+    }
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
+    // e^{-t_j^2}: with P234 (sorted deltas in the ratio 2 : 3 : 4) B^9, B^16, B^36 of
+    // B = e^{-(t_0/6)^2}, one exponential; otherwise one per delta
+    double E0, E1, E2;
+    if (P234) {
+        const double tb = r * p.inv_delta[0] * (1.0 / 6.0);
+        const double B = exp(-tb * tb);
+        const double B4 = (B * B) * (B * B), B8 = B4 * B4, B16 = B8 * B8;
+        E2 = B8 * B;
+        E1 = B16;
+        E0 = (B16 * B16) * B4;
+    } else {
+        const double t0 = r * p.inv_delta[0], t1 = r * p.inv_delta[1], t2 = r * p.inv_delta[2];
+        E0 = exp(-t0 * t0);
+        E1 = exp(-t1 * t1);
+        E2 = exp(-t2 * t2);
+    }
+    double S1, S2, S3;
+    {
+        double a1, a2, a3;
+        smoothing3(r * p.inv_delta[2], E2, p.cutoff, a1, a2, a3);
+        S1 = T.w[2] * a1;
+        S2 = T.w[2] * a2;
+        S3 = T.w[2] * a3;
+        smoothing3(r * p.inv_delta[1], E1, p.cutoff, a1, a2, a3);
+        S1 = __builtin_fma(T.w[1], a1, S1);
+        S2 = __builtin_fma(T.w[1], a2, S2);
+        S3 = __builtin_fma(T.w[1], a3, S3);
+        smoothing3(r * p.inv_delta[0], E0, p.cutoff, a1, a2, a3);
+        S1 = __builtin_fma(T.w[0], a1, S1);
+        S2 = __builtin_fma(T.w[0], a2, S2);
+        S3 = __builtin_fma(T.w[0], a3, S3);
+    }
+    const double ir3 = (ir * ir) * ir;
+    if (SL) {
+        const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
+        const double dg = dx * gx + dy * gy + dz * gz;
+        const double k1 = S1 * ir, k2 = dg * S2 * ir3;
+        A.sl[0][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[0][0]));
+        A.sl[0][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[0][1]));
+        A.sl[0][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[0][2]));
+    }
+    if (DL) {
+        const double nx = T.n[0], ny = T.n[1], nz = T.n[2], b = T.b;
+        const double hx = s.x - T.x0[0], hy = s.y - T.x0[1], hz = s.z - T.x0[2];
+        const double ax = s.q[0] - T.q0[0], ay = s.q[1] - T.q0[1], az = s.q[2] - T.q0[2];
+        const double mx = s.nw[0], my = s.nw[1], mz = s.nw[2];
+        const double na = nx * ax + ny * ay + nz * az;
+        const double nm = nx * mx + ny * my + nz * mz;
+        const double xa = hx * ax + hy * ay + hz * az;
+        const double xm = hx * mx + hy * my + hz * mz;
+        const double xn = hx * nx + hy * ny + hz * nz;
+        const double xx = hx * hx + hy * hy + hz * hz;
+        const double nanm = na * nm;
+        const double c1n = b * nanm - xa * nm - na * xm;
+        const double t1x = nx * c1n - hx * nanm;
+        const double t1y = ny * c1n - hy * nanm;
+        const double t1z = nz * c1n - hz * nanm;
+        const double c2h = b * (xa * nm + na * xm) - xa * xm;
+        const double c2n = b * xa * xm;
+        const double rmb = xx - 2.0 * b * xn;  // r^2 - b^2
+        const double ex = hx * c2h + nx * c2n - rmb * t1x;
+        const double ey = hy * c2h + ny * c2n - rmb * t1y;
+        const double ez = hz * c2h + nz * c2n - rmb * t1z;
+        const double k2 = S2 * ir3, k3 = S3 * (ir3 * (ir * ir));
+        A.dl[0][0] = __builtin_fma(ex, k3, __builtin_fma(t1x, k2, A.dl[0][0]));
+        A.dl[0][1] = __builtin_fma(ey, k3, __builtin_fma(t1y, k2, A.dl[0][1]));
+        A.dl[0][2] = __builtin_fma(ez, k3, __builtin_fma(t1z, k2, A.dl[0][2]));
+    }
+    return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
+}
+
+template <bool SL, bool DL, bool P234>
+__device__ __forceinline__ void near_pair_comb_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
+                                                    const DevParams &p, Acc &A)
+{
+    if (near_pair_comb<SL, DL, P234>(rec64[k], T, p, A)) {
+        int kk = k;
+        asm volatile("" : "+v"(kk));
+        near_pair<SL, DL, true, P234, true>(rec64[kk], T, p, A);
     }
 }
 
@@ -444,14 +580,61 @@ __device__ __forceinline__ void near_pair_sharp_full(const SrcRec<double> *__res
     }
 }
 
-template <typename TC, bool SL, bool DL, bool SHARP, bool P234>
+// Extrapolation weights of eq. (2.10) for a target at signed distance b (the same for the single and
+// double layer and every component); far from the surface the smallest delta alone (w = 1, 0, 0).
+__device__ __forceinline__ void extrap_weights(double b, const DevParams &p, double w[3])
+{
+    w[0] = 1.0;
+    w[1] = 0.0;
+    w[2] = 0.0;
+    const double dmax = p.rho[2] * p.h;  // largest delta (sorted)
+    if (fabs(b) < p.cutoff * dmax) {
+        double al[3], be[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double lam = b * p.inv_delta[j];
+            al[j] = p.rho[j] * I0f(lam);
+            be[j] = p.rho[j] * p.rho[j] * p.rho[j] * I2f(lam);
+        }
+        const double C0 = al[1] * be[2] - al[2] * be[1];
+        const double C1 = al[2] * be[0] - al[0] * be[2];
+        const double C2 = al[0] * be[1] - al[1] * be[0];
+        const double D = C0 + C1 + C2;
+        w[0] = C0 / D;
+        w[1] = C1 / D;
+        w[2] = C2 / D;
+    }
+}
+
+// Candidate steps of 64 loaded together: 4 with single-precision positions; 2 with double-precision
+// ones, whose 4-deep batch costs enough registers to spill (both measured on MI355X).
+template <typename TC>
+constexpr int depth_for() { return sizeof(TC) == 4 ? 4 : 2; }
+constexpr int kRing = 512;   // per-wave ring buffer of near pairs (power of two >= 63 + depth * 64)
+static_assert(kRing >= kWave - 1 + 4 * kWave && (kRing & (kRing - 1)) == 0, "ring buffer size");
+
+template <bool SL, bool DL, bool SHARP, bool P234, bool COMB>
+__device__ __forceinline__ void eval_pair(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
+                                          const DevParams &p, Acc &A)
+{
+    if (SHARP)
+        near_pair_sharp_full<SL, DL>(rec64, k, T, p, A);
+    else if (COMB)
+        near_pair_comb_full<SL, DL, P234>(rec64, k, T, p, A);
+    else
+        near_pair_full<SL, DL, P234, false>(rec64, k, T, p, A);
+}
+
+// COMB (only when no per-delta outputs are asked for): the weights are known before the pair loop and
+// each pair adds K(S), S_k = sum_j w_j s_k(t_j), into one set of accumulators instead of three.
+template <typename TC, bool SL, bool DL, bool SHARP, bool P234, bool COMB>
 __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
                                                                const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
                                                                EvalArgs a, DevParams p, TC rc2,
                                                                const double *__restrict__ part, int nparts)
 {
-    __shared__ int queue_all[kBlock / kWave][2 * kWave];
+    __shared__ int queue_all[kBlock / kWave][kRing];
     // readfirstlane: tells the compiler the wave index (hence the target) is wavefront-uniform, so the
     // target's data live in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
@@ -476,6 +659,7 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
     const bool sharp = p.sharp && T.b == 0.0;
     if (sharp != SHARP) return;  // wavefront-uniform exit
     T.c = SL ? a.f0[3 * t] * T.n[0] + a.f0[3 * t + 1] * T.n[1] + a.f0[3 * t + 2] * T.n[2] : 0.0;
+    if (COMB) extrap_weights(T.b, p, T.w);
     const TC tyx = (TC)(T.y[0] - a.org[0]), tyy = (TC)(T.y[1] - a.org[1]), tyz = (TC)(T.y[2] - a.org[2]);
 
     int ci[3];
@@ -492,80 +676,88 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
 #pragma unroll
         for (int i = 0; i < 3; ++i) A.sl[j][i] = A.dl[j][i] = 0.0;
 
-    int cnt = 0;
+    // Candidates are loaded kDepth steps of 64 at a time, so that kDepth loads are in flight per
+    // wavefront instead of one (the scan is otherwise a chain of dependent load latencies); the near
+    // ones go to a ring buffer in LDS (kRing >= 63 + kDepth * 64 entries) and every full 64 are evaluated.
+    constexpr int kDepth = depth_for<TC>();
+    int head = 0, cnt = 0;  // ring buffer start and length (wavefront-uniform)
     const int z0 = max(ci[2] - 1, 0), z1 = min(ci[2] + 1, grid.g[2] - 1);
     for (int ix = max(ci[0] - 1, 0); ix <= min(ci[0] + 1, grid.g[0] - 1); ++ix) {
         for (int iy = max(ci[1] - 1, 0); iy <= min(ci[1] + 1, grid.g[1] - 1); ++iy) {
             if (z0 > z1) continue;
             const int cb = (ix * grid.g[1] + iy) * grid.g[2];
             const int s0 = cell_start[cb + z0], s1 = cell_start[cb + z1 + 1];
-            for (int base = s0; base < s1; base += kWave) {
-                const int k = base + lane;
-                bool nr = false;
-                if (k < s1) {
-                    const Pos4<TC> q = pos[k];
-                    nr = pair_r2(tyx, tyy, tyz, q.x, q.y, q.z) <= rc2;
+            for (int base = s0; base < s1; base += kDepth * kWave) {
+                Pos4<TC> q[kDepth];
+#pragma unroll
+                for (int u = 0; u < kDepth; ++u) {
+                    const int k = base + u * kWave + lane;
+                    if (k < s1) q[u] = pos[k];
                 }
-                const uint64_t m = __ballot(nr);
-                if (nr) {
-                    const int off = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    queue[cnt + off] = k;
+#pragma unroll
+                for (int u = 0; u < kDepth; ++u) {
+                    const int k = base + u * kWave + lane;
+                    const bool nr = k < s1 && pair_r2(tyx, tyy, tyz, q[u].x, q[u].y, q[u].z) <= rc2;
+                    const uint64_t m = __ballot(nr);
+                    if (nr) {
+                        const int off = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        queue[(head + cnt + off) & (kRing - 1)] = k;
+                    }
+                    cnt += __popcll(m);
                 }
-                cnt += __popcll(m);
-                if (cnt >= kWave) {
+                while (cnt >= kWave) {
                     wave_lds_sync();
-                    const int k2 = queue[lane];
+                    const int k2 = queue[(head + lane) & (kRing - 1)];
                     wave_lds_sync();
-                    if (lane + kWave < cnt) queue[lane] = queue[lane + kWave];
+                    head = (head + kWave) & (kRing - 1);
                     cnt -= kWave;
-                    wave_lds_sync();
-                    if (SHARP)
-                        near_pair_sharp_full<SL, DL>(rec64, k2, T, p, A);
-                    else
-                        near_pair_full<SL, DL, P234>(rec64, k2, T, p, A);
+                    eval_pair<SL, DL, SHARP, P234, COMB>(rec64, k2, T, p, A);
                 }
             }
         }
     }
     wave_lds_sync();
-    if (lane < cnt) {
-        if (SHARP)
-            near_pair_sharp_full<SL, DL>(rec64, queue[lane], T, p, A);
-        else
-            near_pair_full<SL, DL, P234>(rec64, queue[lane], T, p, A);
-    }
+    if (lane < cnt) eval_pair<SL, DL, SHARP, P234, COMB>(rec64, queue[(head + lane) & (kRing - 1)], T, p, A);
 
+    constexpr int NJ = COMB ? 1 : 3;
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             if (SL) A.sl[j][i] = wave_sum(A.sl[j][i]);
             if (DL) A.dl[j][i] = wave_sum(A.dl[j][i]);
         }
 
-    // extrapolation weights (the same for the single and double layer and for every component)
     const double b = T.b;
-    double w0 = 1.0, w1 = 0.0, w2 = 0.0;
-    const double dmax = p.rho[2] * p.h;  // largest delta (sorted)
-    if (!SHARP && fabs(b) < p.cutoff * dmax) {
-        double al[3], be[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double lam = b * p.inv_delta[j];
-            al[j] = p.rho[j] * I0f(lam);
-            be[j] = p.rho[j] * p.rho[j] * p.rho[j] * I2f(lam);
-        }
-        const double C0 = al[1] * be[2] - al[2] * be[1];
-        const double C1 = al[2] * be[0] - al[0] * be[2];
-        const double C2 = al[0] * be[1] - al[1] * be[0];
-        const double D = C0 + C1 + C2;
-        w0 = C0 / D;
-        w1 = C1 / D;
-        w2 = C2 / D;
-    }
     const double chi = b < 0.0 ? 1.0 : (b > 0.0 ? 0.0 : 0.5);
     const double inv8pi = 1.0 / (8.0 * kPi);
+
+    if (COMB) {
+        if (lane < 3) {
+            const int i = lane;
+            if (SL) {
+                double far = 0.0;
+                for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + i) * (size_t)a.m + t];
+                a.u[3 * t + i] = (far + pick3(A.sl[0], i)) * inv8pi;
+            }
+            if (DL) {
+                double far = 0.0;
+                for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + 3 + i) * (size_t)a.m + t];
+                a.v[3 * t + i] = -6.0 * (far + pick3(A.dl[0], i)) * inv8pi + chi * pick3(T.q0, i);
+            }
+        }
+        return;
+    }
+
+    double w0 = 1.0, w1 = 0.0, w2 = 0.0;
+    if (!SHARP) {
+        double w[3];
+        extrap_weights(b, p, w);
+        w0 = w[0];
+        w1 = w[1];
+        w2 = w[2];
+    }
 
     if (lane < 3) {
         const int i = lane;
@@ -600,16 +792,24 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
 {
     const int per_block = kBlock / kWave;
     const int64_t blocks = (a.m + per_block - 1) / per_block;
-    if (p.pow234)
-        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           rec64, pos, cell_start, g, a, p, rc2, part, nparts);
+    const bool comb = a.u_delta == nullptr && a.v_delta == nullptr;
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    if (p.pow234 && comb)
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, true>), grid, block, 0, s, rec64, pos,
+                           cell_start, g, a, p, rc2, part, nparts);
+    else if (p.pow234)
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, false>), grid, block, 0, s, rec64, pos,
+                           cell_start, g, a, p, rc2, part, nparts);
+    else if (comb)
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, true>), grid, block, 0, s, rec64, pos,
+                           cell_start, g, a, p, rc2, part, nparts);
     else
-        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                           rec64, pos, cell_start, g, a, p, rc2, part, nparts);
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, false>), grid, block, 0, s, rec64, pos,
+                           cell_start, g, a, p, rc2, part, nparts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.sharp) return e;
-    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       rec64, pos, cell_start, g, a, p, rc2, part, nparts);
+    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true, false, false>), grid, block, 0, s, rec64, pos,
+                       cell_start, g, a, p, rc2, part, nparts);
     return hipGetLastError();
 }
 
