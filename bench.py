@@ -157,7 +157,19 @@ def cpu_baseline(cfg, target_seconds):
     oracle.dl_cfg(cfg, idx)
     dt = time.perf_counter() - t0
     return {"value": 2.0 * k * n / dt, "unit": "interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s"}
+            "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def log(msg):

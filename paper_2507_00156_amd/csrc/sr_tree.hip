@@ -27,7 +27,9 @@
 // first applies the MAC to the frontier node's ancestors, root first, exactly as the per-target walk
 // would, so every target accepts the same clusters as in one walk; the proxy sum of an accepted
 // ancestor is added by the first frontier node below it.  Output: per split, one partial sum per
-// channel and target (the layout of the direct far field).
+// channel and target (the layout of the direct far field).  The proxies of all clusters (80 B each in
+// FP32, 22 MB at 169k sources, p = 8) do not fit one XCD's 4 MB L2, but the clusters accepted by the
+// targets of one region do: each XCD takes a contiguous eighth of the Morton-sorted targets.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
@@ -528,7 +530,12 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
     int *stk_node = smem + wave * stack_cap * 3;
     uint32_t *stk_mask = (uint32_t *)(stk_node + stack_cap);  // 2 words per entry
     const int m = (int)a.m;
-    const int si = (blockIdx.x * (kBlock / kWave) + wave) * kWave + lane;
+    // workgroups are dispatched round-robin over the 8 XCDs (gridDim.x is a multiple of 8, so the XCD
+    // is blockIdx.x % 8 for every split): XCD x takes the x-th contiguous eighth of the Morton-sorted
+    // targets, a compact region whose accepted clusters' proxies fit its L2
+    const int per_xcd = (int)gridDim.x / 8;
+    const int bx = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    const int si = (bx * (kBlock / kWave) + wave) * kWave + lane;
     const bool valid = si < m;
     const int t = order[valid ? si : m - 1];
 
@@ -613,7 +620,7 @@ hipError_t launch_far_t(const TreeDev &D, const ProxRec<T> *prox, const SrcRec<T
                         double theta2, double rnear2, T rc2, double *part, hipStream_t s)
 {
     const int m = (int)a.m;
-    const int blocks = (m + kBlock - 1) / kBlock;
+    const int blocks = ((m + kBlock - 1) / kBlock + 7) / 8 * 8;
     const size_t shmem = (size_t)(kBlock / kWave) * D.stack_cap * 3 * sizeof(int);
     hipLaunchKernelGGL((tree_far_kernel<T, SL, DL>), dim3(blocks, D.nfront), dim3(kBlock), shmem, s, D.nodes, prox,
                        D.nprox, trec, D.order, D.front, a, theta2, rnear2, rc2, D.stack_cap, part);
