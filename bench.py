@@ -48,6 +48,7 @@ FAR_FLOPS_PER_PAIR_SLDL = 57
 # Per-lane VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32 is not
 # used by this build, so FP32 and FP64 FMAs issue at the same rate.
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6
+TREE_FLOPS_PER_PROXY_PAIR = 75  # SL 24 + DL 40 + d, r^2, rsqrt, 1/r^2, 1/r^3 (11); FMA = 2
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 
 # HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
@@ -207,6 +208,8 @@ def bench_tree(a):
         res[name] = dict(ms=ms, phases=phases, steps=steps)
         outs[name] = [o.clone() for o in out[:2]]
         log(f"[bench tree] {name}: {ms:.3f} ms/step, far {phases[0]:.3f} ms, near+extrap {phases[1]:.3f} ms")
+        if name == "tree":
+            work = ev.tree_work(t.y)  # (target-proxy interactions, leaf pairs, points in accepted clusters)
         ev.close()
     ref = outs["direct_fp64"]
 
@@ -220,8 +223,15 @@ def bench_tree(a):
                     {"workload": "ellipsoid (1,0.8,0.6), h=1/128: N=169342 sources, M=189342 targets, single+double "
                                  "layer, rho=(2,3,4), cutoff 6, treecode degree 8, theta 0.7, leaf 2000, mixed",
                      "n_sources": N, "n_targets": M})
-    out["roofline"] = None
-    out["phases_ms"] = {"far_tree": res["tree"]["phases"][0], "near_extrap": res["tree"]["phases"][1]}
+    far_ms = res["tree"]["phases"][0]
+    flops = TREE_FLOPS_PER_PROXY_PAIR * work[0] + FAR_FLOPS_PER_PAIR_SLDL * work[1]
+    achieved = flops / (far_ms / 1e3) / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "tree_far_kernel (treecode far field; the phase includes the "
+                       "target Morton sort)", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                       "flops_per_proxy_pair": TREE_FLOPS_PER_PROXY_PAIR, "flops_per_leaf_pair": FAR_FLOPS_PER_PAIR_SLDL,
+                       "proxy_pairs_per_launch": work[0], "leaf_pairs_per_launch": work[1], "kernel_ms": far_ms}
+    out["phases_ms"] = {"far_tree": far_ms, "near_extrap": res["tree"]["phases"][1]}
     out["direct_mixed_ms"] = res["direct"]["ms"]
     out["direct_fp64_ms"] = res["direct_fp64"]["ms"]
     out["speedup_vs_direct_mixed"] = res["direct"]["ms"] / ms

@@ -131,6 +131,17 @@ enum { SR_PHASE_FAR = 0, SR_PHASE_NEAR = 1, SR_NPHASES = 2 };
 sr_status sr_set_profiling(sr_ctx *c, int on);
 sr_status sr_get_profile(sr_ctx *c, double *ms, int64_t *evals);
 
+/* Work of the treecode far field (section 3.4, eq. (MAC)) for m targets y (HOST pointer, (m,3)
+ * FP64): *proxy_pairs receives the number of target-proxy interactions (every accepted cluster
+ * contributes (p+1)^3 per target), *leaf_pairs the number of target-point pairs summed directly at
+ * leaves (near pairs included: the kernel visits them and skips their contribution) and, if
+ * cluster_points is not NULL, *cluster_points the number of points inside the accepted clusters
+ * (so cluster_points + leaf_pairs = m N).  Computed on the host with the kernels' acceptance test,
+ * for measurement.  SR_ESTATE unless far_method is SR_TREE and a previous sr_eval built the tree
+ * for the current parameters; SR_EINVAL for NULL pointers or m < 0. */
+sr_status sr_tree_work(sr_ctx *c, int64_t m, const double *y, int64_t *proxy_pairs, int64_t *leaf_pairs,
+                       int64_t *cluster_points);
+
 /* ---------------------------------------------------------------------------------------------
  * Rigid spheres in Stokes flow: the completed double-layer equation for the exterior flow past
  * rigid spheres (Power & Miranda, SIAM J. Appl. Math. 47 (1987)), with every layer integral

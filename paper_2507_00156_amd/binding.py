@@ -21,7 +21,7 @@ _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR
 
 # every symbol the header declares; the CPU test-suite checks that the library exports each one
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
-           "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy",
+           "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
            "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
            "sr_rigid_solve_refined", "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
            "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
@@ -67,6 +67,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_eval.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.sr_set_profiling.argtypes = [vp, C.c_int]
     L.sr_get_profile.argtypes = [vp, d, C.POINTER(C.c_int64)]
+    L.sr_tree_work.argtypes = [vp, i64, vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.sr_rigid_create.argtypes = [C.POINTER(vp), C.c_int]
     L.sr_rigid_destroy.argtypes = [vp]
     L.sr_rigid_set_params.argtypes = [vp, C.POINTER(SrParams)]
@@ -116,7 +117,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_version.argtypes = []
     L.sr_version.restype = C.c_char_p
     for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
-               "sr_set_profiling", "sr_get_profile", "sr_rigid_create", "sr_rigid_destroy", "sr_rigid_set_params",
+               "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+               "sr_rigid_set_params",
                "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_solve_refined",
                "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity"):
         getattr(L, fn).restype = C.c_int
@@ -211,6 +213,20 @@ def sr_get_profile(ctx):
     ne = C.c_int64()
     _check("sr_get_profile", load_library().sr_get_profile(ctx, ms, C.byref(ne)))
     return list(ms), int(ne.value)
+
+
+def sr_tree_work(ctx, y_host):
+    """Treecode far-field work for targets y_host ((m,3) float64 numpy array, host memory):
+    returns (target-proxy interactions, leaf pairs, points inside accepted clusters)."""
+    import numpy as np
+
+    y = np.ascontiguousarray(y_host, dtype=np.float64)
+    if y.ndim != 2 or y.shape[1] != 3:
+        raise ValueError("sr_tree_work: y must be (m, 3)")
+    npx, nlf, ncl = C.c_int64(), C.c_int64(), C.c_int64()
+    _check("sr_tree_work", load_library().sr_tree_work(ctx, int(y.shape[0]), y.ctypes.data_as(C.c_void_p),
+                                                       C.byref(npx), C.byref(nlf), C.byref(ncl)))
+    return int(npx.value), int(nlf.value), int(ncl.value)
 
 
 def _rcheck(fn: str, st: int) -> None:

@@ -600,6 +600,51 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     return SR_OK;
 }
 
+sr_status sr_tree_work(sr_ctx *c, int64_t m, const double *y, int64_t *proxy_pairs, int64_t *leaf_pairs,
+                       int64_t *cluster_points)
+{
+#pragma clang fp contract(off)
+    g_err.clear();
+    if (!c || !proxy_pairs || !leaf_pairs || (m > 0 && !y) || m < 0)
+        return fail(SR_EINVAL, "sr_tree_work: NULL argument or m < 0");
+    if (c->prm.far_method != SR_TREE || c->n == 0 || c->layout_dirty || c->tree_dirty ||
+        c->tree_p != c->prm.tree_degree || c->tree_leaf != c->prm.tree_leaf)
+        return fail(SR_ESTATE, "sr_tree_work: needs far_method SR_TREE and a tree built by a previous sr_eval");
+    const std::vector<TreeNode> &nodes = c->tree.nodes;
+    const int64_t nprox = (int64_t)(c->tree_p + 1) * (c->tree_p + 1) * (c->tree_p + 1);
+    const double theta2 = c->prm.tree_theta * c->prm.tree_theta, rnear2 = c->grid_rnear * c->grid_rnear;
+    int64_t np = 0, nl = 0, nc = 0;
+    std::vector<int> stack;
+    for (int64_t t = 0; t < m; ++t) {
+        const double *yt = y + 3 * t;
+        stack.assign(1, 0);
+        while (!stack.empty()) {
+            const TreeNode &nd = nodes[stack.back()];
+            stack.pop_back();
+            // the kernels' acceptance test, same operations and order
+            double R2 = 0.0, g2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double dc = yt[d] - 0.5 * (nd.lo[d] + nd.hi[d]);
+                R2 += dc * dc;
+                const double gap =
+                    nd.lo[d] - yt[d] > 0.0 ? nd.lo[d] - yt[d] : (yt[d] - nd.hi[d] > 0.0 ? yt[d] - nd.hi[d] : 0.0);
+                g2 += gap * gap;
+            }
+            if (nd.rc2 <= theta2 * R2 && g2 > rnear2) {
+                np += nprox;
+                nc += nd.end - nd.begin;
+            } else if (nd.nchild == 0)
+                nl += nd.end - nd.begin;
+            else
+                for (int k = 0; k < nd.nchild; ++k) stack.push_back(nd.first_child + k);
+        }
+    }
+    *proxy_pairs = np;
+    *leaf_pairs = nl;
+    if (cluster_points) *cluster_points = nc;
+    return SR_OK;
+}
+
 sr_status sr_set_profiling(sr_ctx *c, int on)
 {
     g_err.clear();

@@ -56,6 +56,11 @@ class Evaluator:
                 setattr(p, k, v)
         B.sr_set_params(self.ctx, p)
 
+    def tree_work(self, y_host):
+        """(target-proxy interactions, leaf pairs, points in accepted clusters) of the treecode far field
+        for host targets y_host."""
+        return B.sr_tree_work(self.ctx, y_host)
+
     def set_surface(self, x, nrm, w, stream=None) -> None:
         B.sr_set_surface(self.ctx, x, nrm, w, stream)
         self.n = int(x.shape[0])

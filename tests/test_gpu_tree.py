@@ -93,3 +93,78 @@ def test_tree_c3_sampled(P):
     e1, e2 = rel_err(gu[idx], ou), rel_err(gv[idx], ov)
     print(f"c3 tree mixed: SL {e1:.3e} DL {e2:.3e}", flush=True)
     assert e1 <= 1e-7 and e2 <= 1e-7
+
+
+def _count_tree_work(x, y, leaf, p, theta, rnear):
+    """Independent count of the treecode work: the octree of section 3.4 (midpoint split into 8
+    octants, upper half when x >= mid, empty octants dropped, boxes the bounding boxes of their
+    points, no split when all points fall in one octant) and the MAC r_c^2 <= theta^2 R^2 with the
+    box farther than the near radius, in FP64 operation by operation."""
+    nodes = []
+
+    def build(idx):
+        lo, hi = x[idx].min(0), x[idx].max(0)
+        nd = {"lo": lo, "hi": hi, "n": len(idx), "ch": []}
+        nodes.append(nd)
+        if len(idx) > leaf:
+            mid = (lo + hi) * 0.5
+            oc = (x[idx, 0] >= mid[0]) * 1 + (x[idx, 1] >= mid[1]) * 2 + (x[idx, 2] >= mid[2]) * 4
+            parts = [idx[oc == o] for o in range(8) if (oc == o).any()]
+            if len(parts) > 1:
+                nd["ch"] = [build(q) for q in parts]
+        rc2 = 0.0
+        for d in range(3):
+            e = hi[d] - lo[d]
+            rc2 += 0.25 * e * e
+        nd["rc2"] = rc2
+        return nd
+
+    root = build(np.arange(len(x)))
+    theta2, rnear2, nprox = theta * theta, rnear * rnear, (p + 1) ** 3
+    npx = nlf = ncl = 0
+    stack = [(root, np.arange(len(y)))]
+    while stack:
+        nd, ti = stack.pop()
+        yt = y[ti]
+        R2 = np.zeros(len(ti))
+        g2 = np.zeros(len(ti))
+        for d in range(3):
+            dc = yt[:, d] - 0.5 * (nd["lo"][d] + nd["hi"][d])
+            R2 += dc * dc
+            a, b = nd["lo"][d] - yt[:, d], yt[:, d] - nd["hi"][d]
+            gap = np.where(a > 0.0, a, np.where(b > 0.0, b, 0.0))
+            g2 += gap * gap
+        acc = (nd["rc2"] <= theta2 * R2) & (g2 > rnear2)
+        npx += int(acc.sum()) * nprox
+        ncl += int(acc.sum()) * nd["n"]
+        rest = ti[~acc]
+        if len(rest):
+            if nd["ch"]:
+                stack.extend((c, rest) for c in nd["ch"])
+            else:
+                nlf += len(rest) * nd["n"]
+    return npx, nlf, ncl
+
+
+@pytest.mark.parametrize("p,theta,leaf", [(4, 0.0, 100), (6, 0.7, 200), (4, 0.5, 60)])
+def test_tree_work_counts(P, small, p, theta, leaf):
+    """sr_tree_work (the interaction counts behind the treecode roofline) against an independent
+    count; accepted points plus leaf pairs cover every pair.  (theta = 0 still accepts clusters of
+    zero extent, single points, whose proxy sum is exact.)"""
+    cfg = small
+    s, t = cfg["surf"], cfg["targets"]
+    ev = P.Evaluator(cfg["h"], cfg["rho"], precision=1, far_method=P.SR_TREE, tree_degree=p, tree_theta=theta,
+                     tree_leaf=leaf)
+    ev.set_surface(to_dev(s.x), to_dev(s.normal), to_dev(s.w))
+    ev.set_density(P.SR_SL, to_dev(cfg["f"]))
+    ev.set_density(P.SR_DL, to_dev(cfg["q"]))
+    ev.eval(P.SR_SL | P.SR_DL, to_dev(t.y), to_dev(t.x0), to_dev(t.n0), to_dev(t.b), to_dev(cfg["f0"]),
+            to_dev(cfg["q0"]))
+    npx, nlf, ncl = ev.tree_work(t.y)
+    ev.close()
+    rnear = 6.0 * max(cfg["rho"]) * cfg["h"]
+    ref = _count_tree_work(s.x, t.y, leaf, p, theta, rnear)
+    print(f"tree work p={p} theta={theta} leaf={leaf}: proxy {npx} leaf {nlf} clustered {ncl}", flush=True)
+    assert (npx, nlf, ncl) == ref
+    assert ncl + nlf == t.m * s.n
+    assert npx % (p + 1) ** 3 == 0
