@@ -54,9 +54,9 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 # HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
 # for the kernel source it was measured on: reported as null once the source's hash differs.
-FAR_TRAFFIC = {"bytes": 7.710e7,
+FAR_TRAFFIC = {"bytes": 7.708e7,
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
-                           "d95c67bea2becca5ec78c295215d2eefd9c1f082cf6c66943a5391f4264b5578",
+                           "45c0b3c2bde464463b8ad0ecf0b9e9788bdd5f750bfd242f8e4bc0112e20db87",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
                            "e0b3578ad47e05aed2defd173252a37757c76cdfd81b10c4f108ee30b9e3ec1b"}}
 
@@ -146,12 +146,13 @@ def cpu_baseline(cfg, target_seconds):
     t = cfg["targets"]
     n = cfg["surf"].n
     # calibrate on a small sample, then size the timed sample to about target_seconds
-    idx = np.linspace(0, t.m - 1, 64).astype(np.int64)
+    k0 = 512  # large enough that the thread start-up does not dominate the estimate
+    idx = np.linspace(0, t.m - 1, k0).astype(np.int64)
     t0 = time.perf_counter()
     oracle.sl_cfg(cfg, idx)
     oracle.dl_cfg(cfg, idx)
     dt = time.perf_counter() - t0
-    k = int(np.clip(64 * target_seconds / max(dt, 1e-3), 64, t.m))
+    k = int(np.clip(k0 * target_seconds / max(dt, 1e-3), k0, t.m))
     idx = np.linspace(0, t.m - 1, k).astype(np.int64)
     t0 = time.perf_counter()
     oracle.sl_cfg(cfg, idx)

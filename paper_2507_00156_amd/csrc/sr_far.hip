@@ -29,6 +29,21 @@ struct Org3 {
 
 __device__ __forceinline__ float rsqrt_t(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_t(double v) { return rsqrt(v); }
+// 1/r for a far pair, 0 for a near pair, without a branch (behind a select the compiler would put the
+// double-precision rsqrt sequence in a divergent branch)
+__device__ __forceinline__ float far_ir(float r2, float rc2) { return r2 > rc2 ? __builtin_amdgcn_rsqf(r2) : 0.0f; }
+__device__ __forceinline__ double far_ir(double r2, double rc2)
+{
+    // hardware estimate (relative error ~5e-8 measured on MI355X) and two Newton steps
+    // y <- y + (y/2)(1 - r2 y^2), which reach the library's accuracy (1.4e-16) without its handling
+    // of zero and infinite arguments: a near pair (possibly r2 = 0, giving NaN here) is selected out
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = __builtin_fma(-(r2 * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-(r2 * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    return r2 > rc2 ? y : 0.0;
+}
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -80,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
             for (int k = 0; k < TPL; ++k) {
                 const T dx = ty[k][0] - s.x, dy = ty[k][1] - s.y, dz = ty[k][2] - s.z;
                 const T r2 = pair_r2(ty[k][0], ty[k][1], ty[k][2], s.x, s.y, s.z);
-                const T ir = r2 > rc2 ? rsqrt_t(r2) : (T)0;
+                const T ir = far_ir(r2, rc2);
                 const T ir2 = ir * ir;
                 const T ir3 = ir2 * ir;
                 if (SL) {
