@@ -105,8 +105,9 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const u16 *__restrict__ Ah
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k = kb; k < ke; k += kPad) {
-        bf16x8 ah[2], bh[2], al[2], bl[2];
+    // the operands of step k + kPad are loaded while step k's products run (register double buffer)
+    bf16x8 ah[2], bh[2], al[2], bl[2];
+    auto load = [&](int k) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             ah[i] = *(const bf16x8 *)(Ahi + oa[i] + k);
@@ -116,15 +117,27 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const u16 *__restrict__ Ah
                 bl[i] = *(const bf16x8 *)(Blo + ob[i] + k);
             }
         }
+    };
+    if (kb < ke) load(kb);
+    for (int k = kb; k < ke; k += kPad) {
+        const bf16x8 ch[2] = {ah[0], ah[1]}, dh[2] = {bh[0], bh[1]};
+        bf16x8 cl[2], dl[2];
+        if (PASSES == 3) {
+            cl[0] = al[0];
+            cl[1] = al[1];
+            dl[0] = bl[0];
+            dl[1] = bl[1];
+        }
+        if (k + kPad < ke) load(k + kPad);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (PASSES == 3) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl[i], dh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[i], dl[j], acc[i][j], 0, 0, 0);
                 }
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[i], dh[j], acc[i][j], 0, 0, 0);
             }
     }
     float *Cz = C + (int64_t)blockIdx.z * split_stride;
@@ -460,12 +473,21 @@ sr_status gemm(sr_mlp *Mo, const u16 *Ahi, const u16 *Alo, int64_t lda, const u1
 {
     if (Kpad % kPad != 0 || lda % 8 != 0 || ldb % 8 != 0 || M < 1 || N < 1)
         return mfail(SR_EINVAL, "internal: gemm operand shapes");
+    const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+    if (S == 1 && tiles < 128 && Mo->part) {
+        // few output tiles (batch x width products): split K so that the machine has work, at least
+        // two K steps per split; the partial products are summed by the epilogue in a fixed order
+        const int64_t want = (256 + tiles - 1) / tiles, most = std::max<int64_t>(1, Kpad / (2 * kPad));
+        const int64_t room = (int64_t)Mo->Bpm * Mo->W * kMaxSplit / ((int64_t)M * N);  // split buffer capacity
+        S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(want, most), std::min<int64_t>(room, kMaxSplit)));
+    }
     int64_t kchunk = pad_up((Kpad + S - 1) / S);
     S = (int)((Kpad + kchunk - 1) / kchunk);
     float *dst = S == 1 ? C : Mo->part;
     const int64_t ldd = S == 1 ? ldc : N;
     const int64_t sstride = (int64_t)M * N;
-    if (S > 1 && sstride * S > (int64_t)Mo->Bpm * Mo->W * kMaxSplit) return mfail(SR_EINVAL, "internal: split buffer");
+    if (S > 1 && (!Mo->part || sstride * S > (int64_t)Mo->Bpm * Mo->W * kMaxSplit))
+        return mfail(SR_EINVAL, "internal: split buffer");
     dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64), (unsigned)S);
     if (Mo->passes == 3)
         hipLaunchKernelGGL(gemm_nt_kernel<3>, grid, dim3(256), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, (int)Kpad,
@@ -938,7 +960,8 @@ sr_status sr_mlp_gemm_test(int device, int passes, int M, int N, int K, const fl
     T.Bpm = 32;
     const int64_t Kp = pad_up(K);
     Bf a, b;
-    sr_status st = alloc_bf(&T, a, M, Kp, 0, 0, s);
+    sr_status st = T.alloc(&T.part, (int64_t)T.Bpm * T.W * kMaxSplit) == hipSuccess ? SR_OK : SR_ENOMEM;
+    if (st == SR_OK) st = alloc_bf(&T, a, M, Kp, 0, 0, s);
     if (st == SR_OK) st = alloc_bf(&T, b, N, Kp, 0, 0, s);
     if (st == SR_OK) st = convert(A, M, K, K, M, Kp, a, true, false, s);
     if (st == SR_OK) st = convert(Bm, N, K, K, N, Kp, b, true, false, s);
