@@ -160,7 +160,8 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const float *part, int S,
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= (int64_t)M * N) return;
-    const int row = (int)(i / N), col = (int)(i % N);
+    // M N < 2^31 (checked by the caller): 32-bit division
+    const unsigned iu = (unsigned)i, row = iu / (unsigned)N, col = iu - row * (unsigned)N;
     float s = 0.f;
     for (int z = 0; z < S; ++z) s += part[(int64_t)z * sstride + (int64_t)row * ldp + col];
     if (bias) s += bias[col];
@@ -252,27 +253,30 @@ __global__ __launch_bounds__(256) void contract_back_kernel(int B, int Bp, const
 }
 
 // d = o - y / s (FP64); dout = 2 d / (B P) for rows < B, 0 for padding rows; per-block sums of d^2.
-constexpr int kLossBlocks = 1024;
-__global__ __launch_bounds__(256) void loss_kernel(int B, int Bp, int64_t P, const int64_t *__restrict__ idx,
+// Grid (kLossCols, Bp): block (x, n) covers the columns x * 256 + t, strided by kLossCols * 256, of row n;
+// its sum goes to partial[n kLossCols + x].
+constexpr int kLossCols = 16;
+__global__ __launch_bounds__(256) void loss_kernel(int B, int64_t P, const int64_t *__restrict__ idx,
                                                    const double *__restrict__ y, int64_t ldy,
                                                    const double *__restrict__ s, const float *__restrict__ o,
                                                    int64_t ldo, float *__restrict__ dout, int64_t ldd,
                                                    double *__restrict__ partial)
 {
     __shared__ double red[256];
+    const int n = (int)blockIdx.y;
     const double scale = 2.0 / ((double)B * (double)P);
     double acc = 0.0;
-    const int64_t total = (int64_t)Bp * P;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-        const int n = (int)(i / P);
-        const int64_t p = i % P;
-        float dv = 0.f;
-        if (n < B) {
-            const double d = (double)o[(int64_t)n * ldo + p] - y[row_of(idx, n) * ldy + p] / s[p];
+    const float *on = o + (int64_t)n * ldo;
+    float *dn = dout + (int64_t)n * ldd;
+    if (n < B) {
+        const double *yn = y + row_of(idx, n) * ldy;
+        for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += (int64_t)kLossCols * 256) {
+            const double d = (double)on[p] - yn[p] / s[p];
             acc += d * d;
-            dv = (float)(scale * d);
+            dn[p] = (float)(scale * d);
         }
-        dout[(int64_t)n * ldd + p] = dv;
+    } else {
+        for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P; p += (int64_t)kLossCols * 256) dn[p] = 0.f;
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void loss_kernel(int B, int Bp, int64_t P, con
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[(int64_t)n * kLossCols + blockIdx.x] = red[0];
 }
 
 // one block of 256: each thread sums a fixed strided subset, then a fixed-order tree (reproducible)
@@ -471,7 +475,7 @@ sr_status convert(const float *X, int64_t R, int64_t Cc, int64_t ldx, int64_t Rp
 sr_status gemm(sr_mlp *Mo, const u16 *Ahi, const u16 *Alo, int64_t lda, const u16 *Bhi, const u16 *Blo, int64_t ldb,
                int M, int N, int64_t Kpad, float *C, int64_t ldc, const float *bias, int act, int S, hipStream_t s)
 {
-    if (Kpad % kPad != 0 || lda % 8 != 0 || ldb % 8 != 0 || M < 1 || N < 1)
+    if (Kpad % kPad != 0 || lda % 8 != 0 || ldb % 8 != 0 || M < 1 || N < 1 || (int64_t)M * N >= ((int64_t)1 << 31))
         return mfail(SR_EINVAL, "internal: gemm operand shapes");
     const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
     if (S == 1 && tiles < 128 && Mo->part) {
@@ -544,10 +548,10 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
 {
     const int W = M->W, Bp = (int)pad_up(B), K4 = kNMot * W;
     const int64_t P = M->P, Pp = M->Pp;
-    hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, s, B, Bp, P, idx, y, P, M->scale, M->o, Pp, M->dout,
-                       Pp, M->lpart);
+    hipLaunchKernelGGL(loss_kernel, dim3(kLossCols, (unsigned)Bp), dim3(256), 0, s, B, P, idx, y, P, M->scale, M->o, Pp,
+                       M->dout, Pp, M->lpart);
     MHIP(hipGetLastError());
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, M->lpart, kLossBlocks,
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, M->lpart, Bp * kLossCols,
                        1.0 / ((double)B * (double)P), M->lval);
     MHIP(hipGetLastError());
     MSR(convert(M->dout, Bp, P, Pp, Bp, Pp, M->bdout, true, true, s));
@@ -723,7 +727,7 @@ sr_status sr_mlp_create(sr_mlp **out, int device, int width, int64_t nout, int m
     MC(M->alloc(&M->d2, Bpm * W));
     MC(M->alloc(&M->d1, Bpm * W));
     MC(M->alloc(&M->part, Bpm * W * kMaxSplit));
-    MC(M->alloc(&M->lpart, kLossBlocks));
+    MC(M->alloc(&M->lpart, (int64_t)Bpm * kLossCols));
     MC(M->alloc(&M->lval, 1));
     MCS(alloc_bf(M, M->w2, W, W, W, W, s));
     MCS(alloc_bf(M, M->w3, W, W, W, W, s));
