@@ -163,6 +163,86 @@ def cpu_baseline(cfg, target_seconds):
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
+def cpu_baseline_tree(cfg, target_seconds, p=8, theta=0.7, leaf=2000):
+    """The oracle treecode (its own octree, proxies and modified weights, built per call) on an evenly
+    spaced sample of the targets; scaled to equivalent target-source interactions/s."""
+    import oracle
+
+    t, n = cfg["targets"], cfg["surf"].n
+
+    def run(k):
+        idx = np.linspace(0, t.m - 1, k).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.tree_cfg(cfg, idx, p=p, theta=theta, leaf=leaf)
+        return time.perf_counter() - t0
+
+    # every call builds the tree (a fixed cost a) and then pays b per target: fit both on two sizes and
+    # size the sample so that the whole call takes about target_seconds
+    k0 = 256
+    t1, t2 = run(k0), run(4 * k0)
+    b = max((t2 - t1) / (3 * k0), 1e-6)
+    a = max(t1 - b * k0, 0.0)
+    k = int(np.clip((target_seconds - a) / b, k0, t.m))
+    idx = np.linspace(0, t.m - 1, k).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.tree_cfg(cfg, idx, p=p, theta=theta, leaf=leaf)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * k * n / dt, "unit": "interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, treecode degree {p}, theta {theta}, "
+                      f"leaf {leaf}, tree set-up included, {dt:.1f} s", "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_baseline_rigid(h, gap, q, matvecs, target_seconds):
+    """The oracle's rigid-sphere operator (FP64, direct sums) on an evenly spaced sample of rows, scaled
+    to one matrix-vector product and multiplied by the number of products the GPU solve used."""
+    import oracle
+    import workload
+    from oracle.rigid import RigidProblem, Sphere
+
+    cen, rad, surfs = workload.two_spheres(h, gap)
+    prob = RigidProblem([Sphere(sf, c, a, h) for sf, c, a in zip(surfs, cen, rad)], h, full=False)
+    k0 = 64
+    rows = np.linspace(0, prob.ntot - 1, k0).astype(np.int64)
+    t0 = time.perf_counter()
+    prob.matvec_rows(q, rows)
+    dt0 = time.perf_counter() - t0
+    k = int(np.clip(k0 * target_seconds / max(dt0, 1e-3), k0, prob.ntot))
+    rows = np.linspace(0, prob.ntot - 1, k).astype(np.int64)
+    t0 = time.perf_counter()
+    prob.matvec_rows(q, rows)
+    dt = time.perf_counter() - t0
+    mv = dt * prob.ntot / k
+    return {"value": mv * matvecs, "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle operator on {k} of {prob.ntot} rows ({dt:.1f} s), scaled to one product ({mv:.1f} s) "
+                      f"x the {matvecs} products of the GPU solve at gap {gap}", "matvec_s": mv,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_baseline_mlp(width, nout, batch, target_seconds):
+    """The oracle network (numpy FP64: forward, gradients, Adam) at the same shape; training steps/s."""
+    import workload
+    from oracle import mlp as omlp
+
+    p = workload.mlp_init(width, nout, 5)
+    rng = np.random.default_rng(2)
+    g, m = workload.warmstart_samples(batch, 3)
+    m = m.reshape(batch, 12)
+    y = rng.standard_normal((batch, nout))
+    opt = omlp.Adam(lr=1e-4)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o, cache = omlp.forward(p, g, m, -2.760730458931123, 1.151292546497023)
+        gr = omlp.backward(p, cache, o, y)
+        opt.step(p, gr)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_seconds or steps >= 200:
+            break
+    return {"value": steps / dt, "unit": "steps/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"{steps} training steps (batch {batch}) of the numpy FP64 oracle, {dt:.1f} s; cores = the "
+                      "threads numpy's BLAS may use", "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -239,6 +319,8 @@ def bench_tree(a):
     out["error_vs_fp64_direct"] = {"sl": rel(outs["tree"][0], ref[0]), "dl": rel(outs["tree"][1], ref[1])}
     out["error_direct_mixed_vs_fp64_direct"] = {"sl": rel(outs["direct"][0], ref[0]),
                                                 "dl": rel(outs["direct"][1], ref[1])}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_tree(cfg, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -322,6 +404,13 @@ def bench_gmres(a):
     out["matvec_ms_mixed"] = mv_ms
     out["matvec_interactions_per_s"] = 2 * nsph * ntot / (mv_ms / 1e3)
     out["matvec_ms_mixed_surface_sharp"] = mv_sharp_ms
+    if not a.no_cpu_baseline:
+        # matrix-vector products per solve: the inner iterations plus one FP64 residual per correction and
+        # the initial one; the operator's cost hardly depends on the gap, so it is timed at the first gap
+        nmv = float(np.mean([v["inner_iterations"] + v["fp64_corrections"] + 1 for v in per_gap_tree.values()]))
+        ntot_cpu = sum(sf.n for sf in workload.two_spheres(h, 0.1)[2])
+        qs = np.random.default_rng(11).standard_normal((ntot_cpu, 3))
+        out["cpu_baseline"] = cpu_baseline_rigid(h, 0.1, qs, round(nmv), a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -380,6 +469,8 @@ def bench_mlp(a):
                        "bytes_per_launch": adam_bytes, "kernel_ms": ph[2]}
     out["phases_ms_per_step"] = {"forward": ph[0], "backward": ph[1], "adam": ph[2], "weight_copies": ph[3]}
     out["inference_ms_batch1"] = inf_ms
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_mlp(W_, nout, batch, a.cpu_seconds)
     print(json.dumps(out), flush=True)
     net.close()
 
