@@ -54,11 +54,11 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 # HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
 # for the kernel source it was measured on: reported as null once the source's hash differs.
-FAR_TRAFFIC = {"bytes": 7.708e7,
+FAR_TRAFFIC = {"bytes": 7.711e7,
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
-                           "45c0b3c2bde464463b8ad0ecf0b9e9788bdd5f750bfd242f8e4bc0112e20db87",
+                           "c00c9eb90f9431c5e23ee63abbcec154313af1b507f1a199532bffdcd289d029",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "e0b3578ad47e05aed2defd173252a37757c76cdfd81b10c4f108ee30b9e3ec1b"}}
+                           "51107e6bb0f57184e4ee16caf498c1b34c4d20ac4d7a40a6878f044c244c0e24"}}
 
 
 def far_traffic():

@@ -557,6 +557,7 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     dp.pow234 = (2.0 * dp.rho[1] == 3.0 * dp.rho[0] && dp.rho[2] == 2.0 * dp.rho[0]) ? 1 : 0;
     dp.sharp = c->prm.surface_sharp ? 1 : 0;
     dp.inv_dsharp = 1.0 / (c->prm.sharp_rho * c->prm.h);
+    dp.rsharp = dp.sharp ? std::min(dp.rnear, c->prm.cutoff * c->prm.sharp_rho * c->prm.h) : dp.rnear;
 
     const bool tree = c->prm.far_method == SR_TREE;
     int nparts = kFarSplits;
@@ -589,9 +590,11 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
             ext = std::max(ext, root.hi[d] - root.lo[d] + 2.0 * dp.rnear);
         }
         SR_HIP(launch_target_order(y, (int)m, lo, 1024.0 / ext, c->tdev, s));
-        SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear, c->part.p, s));
+        SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear, dp.rsharp, dp.sharp,
+                               c->part.p, s));
     } else {
-        SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, c->part.p, s));
+        SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, dp.rsharp,
+                                 dp.sharp, c->part.p, s));
     }
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p, c->cell_start.p,

@@ -10,7 +10,8 @@
 //   - the source index is wavefront-uniform, so each record is fetched once per wavefront through
 //     the scalar data cache and feeds the VALU as scalar operands: no LDS traffic, no barriers;
 //   - near pairs (r^2 <= rc2 by the shared pair_r2 test) are selected out (not multiplied by zero:
-//     r can be 0);
+//     r can be 0); rc2 is the target's: the smaller radius of the modified smoothing for targets on
+//     the surface when it is selected, the near radius otherwise;
 //   - mixed precision: pair kernels in FP32, 32-pair FP32 partial sums promoted to FP64;
 //   - output: per-split partial sums part[split][channel][target], channel 0..2 = single-layer
 //     sum of S g, channel 3..5 = sum of d (d.a)(d.m) / r^5 (the -6 and 1/(8 pi) are applied
@@ -47,12 +48,15 @@ __device__ __forceinline__ double far_ir(double r2, double rc2)
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <typename T, bool SL, bool DL, int TPL>
+// PT: per-target near radius (the modified smoothing is on); otherwise rc2 for every target, kept in a
+// scalar register (a per-lane radius costs 4% of the mixed-precision kernel)
+template <typename T, bool SL, bool DL, int TPL, bool PT>
 __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__restrict__ src, int n, int chunk,
                                                             const double *__restrict__ y,
                                                             const double *__restrict__ n0,
                                                             const double *__restrict__ f0,
-                                                            const double *__restrict__ q0, int m, T rc2,
+                                                            const double *__restrict__ q0,
+                                                            const double *__restrict__ bt, int m, T rc2, T rc2s,
                                                             Org3 org, double *__restrict__ part)
 {
     const int split = blockIdx.x % kFarSplits;
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
     const int p0 = split * chunk;
     const int p1 = min(n, p0 + chunk);
 
-    T ty[TPL][3], tc[TPL], tq[TPL][3];
+    T ty[TPL][3], tc[TPL], tq[TPL][3], tr2[TPL];
     int tix[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -73,6 +77,8 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
         if (SL) tc[k] = (T)(f0[3 * tt] * n0[3 * tt] + f0[3 * tt + 1] * n0[3 * tt + 1] + f0[3 * tt + 2] * n0[3 * tt + 2]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) tq[k][i] = DL ? (T)q0[3 * tt + i] : (T)0;
+        // a target on the surface under the modified smoothing has the smaller near radius
+        tr2[k] = (PT && bt[tt] == 0.0) ? rc2s : rc2;
     }
 
     double acc[TPL][6];
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
             for (int k = 0; k < TPL; ++k) {
                 const T dx = ty[k][0] - s.x, dy = ty[k][1] - s.y, dz = ty[k][2] - s.z;
                 const T r2 = pair_r2(ty[k][0], ty[k][1], ty[k][2], s.x, s.y, s.z);
-                const T ir = far_ir(r2, rc2);
+                const T ir = far_ir(r2, tr2[k]);
                 const T ir2 = ir * ir;
                 const T ir3 = ir2 * ir;
                 if (SL) {
@@ -140,35 +146,42 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
 }
 
 template <typename T, bool SL, bool DL>
-hipError_t launch_t(const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, double *part, hipStream_t s)
+hipError_t launch_t(const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, T rc2s, int sharp, double *part,
+                    hipStream_t s)
 {
     constexpr int TPL = 2;
     const int m = (int)a.m;
     const int tiles = (m + kBlock * TPL - 1) / (kBlock * TPL);
     const int chunk = (int)((n + kFarSplits - 1) / kFarSplits);
     dim3 grid(tiles * kFarSplits), block(kBlock);
-    hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0, a.f0,
-                       a.q0, m, rc2, Org3{a.org[0], a.org[1], a.org[2]}, part);
+    if (sharp)
+        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, true>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0,
+                           a.f0, a.q0, a.b, m, rc2, rc2s, Org3{a.org[0], a.org[1], a.org[2]}, part);
+    else
+        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, false>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0,
+                           a.f0, a.q0, a.b, m, rc2, rc2s, Org3{a.org[0], a.org[1], a.org[2]}, part);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t dispatch(int layers, const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, double *part,
-                    hipStream_t s)
+hipError_t dispatch(int layers, const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, T rc2s, int sharp,
+                    double *part, hipStream_t s)
 {
-    if (layers == (SR_SL | SR_DL)) return launch_t<T, true, true>(rec, n, a, rc2, part, s);
-    if (layers == SR_SL) return launch_t<T, true, false>(rec, n, a, rc2, part, s);
-    return launch_t<T, false, true>(rec, n, a, rc2, part, s);
+    if (layers == (SR_SL | SR_DL)) return launch_t<T, true, true>(rec, n, a, rc2, rc2s, sharp, part, s);
+    if (layers == SR_SL) return launch_t<T, true, false>(rec, n, a, rc2, rc2s, sharp, part, s);
+    return launch_t<T, false, true>(rec, n, a, rc2, rc2s, sharp, part, s);
 }
 
 }  // namespace
 
 hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
-                             int64_t n, const EvalArgs &a, double rnear, double *part, hipStream_t s)
+                             int64_t n, const EvalArgs &a, double rnear, double rsharp, int sharp, double *part,
+                             hipStream_t s)
 {
-    const double rc2 = rnear * rnear;
-    if (precision == SR_MIXED) return dispatch<float>(layers, rec32, n, a, (float)rc2, part, s);
-    return dispatch<double>(layers, rec64, n, a, rc2, part, s);
+    const double rc2 = rnear * rnear, rc2s = rsharp * rsharp;
+    if (precision == SR_MIXED)
+        return dispatch<float>(layers, rec32, n, a, (float)rc2, (float)rc2s, sharp, part, s);
+    return dispatch<double>(layers, rec64, n, a, rc2, rc2s, sharp, part, s);
 }
 
 }  // namespace sr

@@ -88,6 +88,7 @@ struct DevParams {
     int pow234;          // the sorted deltas are in the ratio 2 : 3 : 4 (exp(-t_j^2) by powers of one exp)
     int sharp;           // targets on the surface (b == 0) use the modified smoothing at one delta
     double inv_dsharp;   // 1 / that delta
+    double rsharp;       // cutoff * that delta: the near radius of those targets (rnear otherwise)
 };
 
 // ---- kernel launchers (return hipSuccess or the launch error) ----
@@ -95,8 +96,10 @@ hipError_t launch_pack(const double *x, const double *nrm, const double *w, cons
                        const int64_t *perm, int64_t n, const double org[3], SrcRec<double> *rec64, SrcRec<float> *rec32,
                        Pos4<double> *pos64, Pos4<float> *pos32, hipStream_t s);
 
+// rnear: near radius of every target; with sharp, targets with b == 0 use rsharp (<= rnear) instead
 hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
-                             int64_t n, const EvalArgs &a, double rnear, double *part, hipStream_t s);
+                             int64_t n, const EvalArgs &a, double rnear, double rsharp, int sharp, double *part,
+                             hipStream_t s);
 
 hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
                                 const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,

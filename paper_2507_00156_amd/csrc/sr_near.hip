@@ -631,7 +631,7 @@ template <typename TC, bool SL, bool DL, bool SHARP, bool P234, bool COMB>
 __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
                                                                const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
-                                                               EvalArgs a, DevParams p, TC rc2,
+                                                               EvalArgs a, DevParams p, TC rc2, TC rc2s,
                                                                const double *__restrict__ part, int nparts)
 {
     __shared__ int queue_all[kBlock / kWave][kRing];
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
 #pragma unroll
                 for (int u = 0; u < kDepth; ++u) {
                     const int k = base + u * kWave + lane;
-                    const bool nr = k < s1 && pair_r2(tyx, tyy, tyz, q[u].x, q[u].y, q[u].z) <= rc2;
+                    const bool nr = k < s1 && pair_r2(tyx, tyy, tyz, q[u].x, q[u].y, q[u].z) <= (SHARP ? rc2s : rc2);
                     const uint64_t m = __ballot(nr);
                     if (nr) {
                         const int off = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -793,23 +793,24 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
     const int per_block = kBlock / kWave;
     const int64_t blocks = (a.m + per_block - 1) / per_block;
     const bool comb = a.u_delta == nullptr && a.v_delta == nullptr;
+    const TC rc2s = (TC)(p.rsharp * p.rsharp);  // near radius of the surface targets of the SHARP instance
     const dim3 grid((unsigned)blocks), block(kBlock);
     if (p.pow234 && comb)
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, true>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts);
     else if (p.pow234)
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, false>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts);
     else if (comb)
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, true>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts);
     else
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, false>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.sharp) return e;
     hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true, false, false>), grid, block, 0, s, rec64, pos,
-                       cell_start, g, a, p, rc2, part, nparts);
+                       cell_start, g, a, p, rc2, rc2s, part, nparts);
     return hipGetLastError();
 }
 

@@ -77,7 +77,8 @@ hipError_t launch_target_order(const double *y, int m, const double lo[3], doubl
 size_t target_sort_tmp_bytes(int m);
 
 // Far field by the treecode into part[split][channel][target], D.nfront splits.
+// rnear / rsharp / sharp: as for launch_far_direct
 hipError_t launch_tree_far(int precision, int layers, const TreeDev &D, const EvalArgs &a, double theta,
-                           double rnear, double *part, hipStream_t s);
+                           double rnear, double rsharp, int sharp, double *part, hipStream_t s);
 
 }  // namespace sr

@@ -427,6 +427,7 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 template <typename T>
 struct Lane {
     T y[3], c, q0[3];
+    T rc2;  // the target's near radius squared (smaller for surface targets under the modified smoothing)
 };
 
 constexpr int kPromote = 32;  // terms summed in T before promotion to FP64
@@ -477,7 +478,7 @@ __device__ __forceinline__ void proxy_sum(const ProxRec<T> *__restrict__ pr, int
 }
 
 template <typename T, bool SL, bool DL>
-__device__ __forceinline__ void leaf_sum(const SrcRec<T> *__restrict__ src, int b0, int b1, const Lane<T> &L, T rc2,
+__device__ __forceinline__ void leaf_sum(const SrcRec<T> *__restrict__ src, int b0, int b1, const Lane<T> &L,
                                          double acc[6])
 {
     SrcRec<T> nxt = src[b0];
@@ -489,7 +490,7 @@ __device__ __forceinline__ void leaf_sum(const SrcRec<T> *__restrict__ src, int 
             nxt = src[min(k + 1, b1 - 1)];
             const T dx = L.y[0] - s.x, dy = L.y[1] - s.y, dz = L.y[2] - s.z;
             const T r2 = pair_r2(L.y[0], L.y[1], L.y[2], s.x, s.y, s.z);
-            const T ir = r2 > rc2 ? rsqrt_t(r2) : (T)0;  // near pairs belong to the near-field kernel
+            const T ir = r2 > L.rc2 ? rsqrt_t(r2) : (T)0;  // near pairs belong to the near-field kernel
             const T ir2 = ir * ir, ir3 = ir2 * ir;
             if (SL) {
                 const T gx = fma_t(-L.c, s.nw[0], s.fw[0]);
@@ -521,8 +522,8 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
                                                           const SrcRec<T> *__restrict__ trec,
                                                           const int *__restrict__ order,
                                                           const FrontierRec *__restrict__ front, EvalArgs a,
-                                                          double theta2, double rnear2, T rc2, int stack_cap,
-                                                          double *__restrict__ part)
+                                                          double theta2, double rnear2, T rc2, T rc2s, int sharp,
+                                                          int stack_cap, double *__restrict__ part)
 {
     extern __shared__ int smem[];
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
@@ -549,6 +550,8 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
     }
     L.c = SL ? (T)(a.f0[3 * t] * a.n0[3 * t] + a.f0[3 * t + 1] * a.n0[3 * t + 1] + a.f0[3 * t + 2] * a.n0[3 * t + 2])
              : (T)0;
+    // the MAC keeps the full near radius (conservative); the leaf sums skip the target's own near pairs
+    L.rc2 = (sharp && a.b[t] == 0.0) ? rc2s : rc2;
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
     // this split's frontier node: first its ancestors (root first), as the per-target walk would
@@ -589,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
         }
         if (rm) {
             if (nd.nchild == 0) {
-                if ((rm >> lane) & 1) leaf_sum<T, SL, DL>(trec, nd.begin, nd.end, L, rc2, acc);
+                if ((rm >> lane) & 1) leaf_sum<T, SL, DL>(trec, nd.begin, nd.end, L, acc);
             } else {
                 __builtin_amdgcn_wave_barrier();
                 if (lane == 0) {
@@ -617,13 +620,13 @@ __global__ __launch_bounds__(kBlock) void tree_far_kernel(const TreeNode *__rest
 
 template <typename T, bool SL, bool DL>
 hipError_t launch_far_t(const TreeDev &D, const ProxRec<T> *prox, const SrcRec<T> *trec, const EvalArgs &a,
-                        double theta2, double rnear2, T rc2, double *part, hipStream_t s)
+                        double theta2, double rnear2, T rc2, T rc2s, int sharp, double *part, hipStream_t s)
 {
     const int m = (int)a.m;
     const int blocks = ((m + kBlock - 1) / kBlock + 7) / 8 * 8;
     const size_t shmem = (size_t)(kBlock / kWave) * D.stack_cap * 3 * sizeof(int);
     hipLaunchKernelGGL((tree_far_kernel<T, SL, DL>), dim3(blocks, D.nfront), dim3(kBlock), shmem, s, D.nodes, prox,
-                       D.nprox, trec, D.order, D.front, a, theta2, rnear2, rc2, D.stack_cap, part);
+                       D.nprox, trec, D.order, D.front, a, theta2, rnear2, rc2, rc2s, sharp, D.stack_cap, part);
     return hipGetLastError();
 }
 
@@ -671,21 +674,23 @@ size_t target_sort_tmp_bytes(int m)
 }
 
 hipError_t launch_tree_far(int precision, int layers, const TreeDev &D, const EvalArgs &a, double theta,
-                           double rnear, double *part, hipStream_t s)
+                           double rnear, double rsharp, int sharp, double *part, hipStream_t s)
 {
 #pragma clang fp contract(off)
-    const double theta2 = theta * theta, rnear2 = rnear * rnear;
+    const double theta2 = theta * theta, rnear2 = rnear * rnear, rs2 = rsharp * rsharp;
     if (precision == SR_MIXED) {
-        const float rc2 = (float)rnear2;
+        const float rc2 = (float)rnear2, rc2s = (float)rs2;
         if (layers == (SR_SL | SR_DL))
-            return launch_far_t<float, true, true>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, part, s);
-        if (layers == SR_SL) return launch_far_t<float, true, false>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, part, s);
-        return launch_far_t<float, false, true>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, part, s);
+            return launch_far_t<float, true, true>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, rc2s, sharp, part, s);
+        if (layers == SR_SL)
+            return launch_far_t<float, true, false>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, rc2s, sharp, part, s);
+        return launch_far_t<float, false, true>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, rc2s, sharp, part, s);
     }
     if (layers == (SR_SL | SR_DL))
-        return launch_far_t<double, true, true>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, part, s);
-    if (layers == SR_SL) return launch_far_t<double, true, false>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, part, s);
-    return launch_far_t<double, false, true>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, part, s);
+        return launch_far_t<double, true, true>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, rs2, sharp, part, s);
+    if (layers == SR_SL)
+        return launch_far_t<double, true, false>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, rs2, sharp, part, s);
+    return launch_far_t<double, false, true>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, rs2, sharp, part, s);
 }
 
 }  // namespace sr
