@@ -68,6 +68,33 @@ def test_theta_zero_is_direct(P, small):
     assert rel_err(gu, du) <= 1e-12 and rel_err(gv, dv) <= 1e-12
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_theta_zero_is_direct_with_modified_smoothing(P, small, precision):
+    """With the on-surface modified smoothing, surface targets have a smaller near radius than the
+    others; at theta = 0 the treecode's leaf sums must take exactly the pairs the direct far field
+    takes (each target's own radius), so the two far fields agree to rounding."""
+    import torch
+
+    cfg = small
+    s, t = cfg["surf"], cfg["targets"]
+    outs = []
+    for far in (P.SR_DIRECT, P.SR_TREE):
+        ev = P.Evaluator(cfg["h"], cfg["rho"], precision=precision, far_method=far, tree_degree=4, tree_theta=0.0,
+                         tree_leaf=100, surface_sharp=True, sharp_rho=3.0)
+        ev.set_surface(to_dev(s.x), to_dev(s.normal), to_dev(s.w))
+        ev.set_density(P.SR_SL, to_dev(cfg["f"]))
+        ev.set_density(P.SR_DL, to_dev(cfg["q"]))
+        u, v = ev.eval(P.SR_SL | P.SR_DL, to_dev(t.y), to_dev(t.x0), to_dev(t.n0), to_dev(t.b), to_dev(cfg["f0"]),
+                       to_dev(cfg["q0"]))
+        torch.cuda.synchronize()
+        outs.append((u.cpu().numpy(), v.cpu().numpy()))
+        ev.close()
+    e1, e2 = rel_err(outs[1][0], outs[0][0]), rel_err(outs[1][1], outs[0][1])
+    print(f"theta 0 with modified smoothing, precision {precision}: SL {e1:.2e} DL {e2:.2e}", flush=True)
+    bar = 1e-12 if precision == 0 else 1e-6
+    assert e1 <= bar and e2 <= bar
+
+
 def test_tree_error_vs_direct_decreases_with_p(P):
     cfg = workload.build_config("c2", m_near=2000)
     du, dv = gpu_eval(cfg, 3, 0)
