@@ -142,15 +142,29 @@ __global__ __launch_bounds__(kRed) void strengths_kernel(const double *__restric
         for (int c = 0; c < 6; ++c) part[6 * blockIdx.x + c] = sh[c][0];
 }
 
-// second pass of the strengths: FL[m][c] = sum over blocks, in block order
-__global__ void strengths_final_kernel(const double *__restrict__ part, int nsph, int nblk, double *__restrict__ FL)
+// fixed-order sum of the kRed values in sh (a binary tree); the result is in sh[0]
+__device__ __forceinline__ void block_tree_sum(double *sh)
 {
-    const int i = threadIdx.x;  // m * 6 + c
-    if (i >= 6 * nsph) return;
+    __syncthreads();
+    for (int st = kRed / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+}
+
+// second pass of the strengths: FL[m][c] = sum over the blocks' partial sums; one workgroup per
+// (m, c), each thread a fixed strided subset, then a fixed-order tree (reproducible)
+__global__ __launch_bounds__(kRed) void strengths_final_kernel(const double *__restrict__ part, int nsph, int nblk,
+                                                               double *__restrict__ FL)
+{
+    __shared__ double sh[kRed];
+    const int i = (int)blockIdx.x;  // m * 6 + c
     const int m = i / 6, c = i % 6;
     double a = 0.0;
-    for (int b = 0; b < nblk; ++b) a += part[((size_t)m * nblk + b) * 6 + c];
-    FL[i] = a;
+    for (int b = (int)threadIdx.x; b < nblk; b += kRed) a += part[((size_t)m * nblk + b) * 6 + c];
+    sh[threadIdx.x] = a;
+    block_tree_sum(sh);
+    if (threadIdx.x == 0) FL[i] = sh[0];
 }
 
 // out = [-1/2 q] + sum_m v_m + sum_m C_m(y), FL[m] = (F_m, L_m)
@@ -205,14 +219,18 @@ __global__ __launch_bounds__(kRed) void mdot_kernel(const double *__restrict__ V
     }
 }
 
-// second pass: res[k] = sum_b part[b][k] (fixed order)
-__global__ void mdot_final_kernel(const double *__restrict__ part, int nblk, int K, double *__restrict__ res)
+// second pass: res[k] = sum_b part[b][k]; one workgroup per k, each thread a fixed strided subset of
+// the blocks, then a fixed-order tree (reproducible)
+__global__ __launch_bounds__(kRed) void mdot_final_kernel(const double *__restrict__ part, int nblk, int K,
+                                                          double *__restrict__ res)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * K + k];
-    res[k] = s;
+    __shared__ double sh[kRed];
+    const int k = (int)blockIdx.x;
+    double a = 0.0;
+    for (int b = (int)threadIdx.x; b < nblk; b += kRed) a += part[(size_t)b * K + k];
+    sh[threadIdx.x] = a;
+    block_tree_sum(sh);
+    if (threadIdx.x == 0) res[k] = sh[0];
 }
 
 // w -= sum_k V[k] c[k]   (c on the device)
@@ -422,8 +440,8 @@ sr_status rigid_matvec(sr_rigid *R, const std::vector<sr_ctx *> &ctx, const doub
         }
     }
     if (R->completion) {
-        hipLaunchKernelGGL(strengths_final_kernel, dim3(1), dim3(64 * ((6 * R->nsph + 63) / 64)), 0, s, R->part.p,
-                           R->nsph, kRedBlocks, R->FL.p);
+        hipLaunchKernelGGL(strengths_final_kernel, dim3(6 * R->nsph), dim3(kRed), 0, s, R->part.p, R->nsph, kRedBlocks,
+                           R->FL.p);
         RHIP(hipGetLastError());
     }
     hipLaunchKernelGGL(assemble_kernel, dim3(nblocks(N)), dim3(256), 0, s, q, R->x.p, N, R->nsph, R->vall.p,
@@ -438,7 +456,7 @@ sr_status mdot(sr_rigid *R, const double *V, size_t ld, int K, const double *w, 
     RHIP(R->red.alloc((size_t)kRedBlocks * K));
     hipLaunchKernelGGL(mdot_kernel, dim3(kRedBlocks), dim3(kRed), 0, s, V, ld, K, w, n, R->red.p);
     RHIP(hipGetLastError());
-    hipLaunchKernelGGL(mdot_final_kernel, dim3((K + 63) / 64), dim3(64), 0, s, R->red.p, kRedBlocks, K, R->coef.p);
+    hipLaunchKernelGGL(mdot_final_kernel, dim3(K), dim3(kRed), 0, s, R->red.p, kRedBlocks, K, R->coef.p);
     RHIP(hipGetLastError());
     if (hres) {
         RHIP(hipMemcpyAsync(hres, R->coef.p, K * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -709,8 +727,8 @@ sr_status sr_rigid_velocity(sr_rigid *R, const double *q, int64_t m, const doubl
     }
     Buf<double> FL;
     RHIP(FL.alloc((size_t)R->nsph * 6));
-    hipLaunchKernelGGL(strengths_final_kernel, dim3(1), dim3(64 * ((6 * R->nsph + 63) / 64)), 0, s, part.p, R->nsph,
-                       kRedBlocks, FL.p);
+    hipLaunchKernelGGL(strengths_final_kernel, dim3(6 * R->nsph), dim3(kRed), 0, s, part.p, R->nsph, kRedBlocks,
+                       FL.p);
     RHIP(hipGetLastError());
     hipLaunchKernelGGL(assemble_kernel, dim3(nblocks(m)), dim3(256), 0, s, q, y, m, R->nsph, vv.p, R->dcenters.p,
                        FL.p, u, 0.0, 1.0, 1);
