@@ -85,9 +85,12 @@ def parse():
     ap.add_argument("--workload", choices=["c2", "tree", "gmres", "mlp", "warmstart", "table1", "sweep", "drops"],
                     default="c2")
     ap.add_argument("--drops-max", type=int, default=128, help="drops: finest 1/h")
-    ap.add_argument("--train-solves", type=int, default=800, help="warmstart: training solves")
-    ap.add_argument("--train-steps", type=int, default=60000, help="warmstart: optimizer steps")
+    ap.add_argument("--train-solves", type=int, default=792, help="warmstart: training solves")
+    ap.add_argument("--train-steps", type=int, default=500000, help="warmstart: optimizer steps")
     ap.add_argument("--heldout", type=int, default=60, help="warmstart: held-out solves")
+    ap.add_argument("--ws-design", choices=("unit-log", "unit", "random"), default="unit",
+                    help="warmstart: the 12 unit motions per gap at log-spaced or random gaps, or 4 random "
+                         "motions per random gap")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (calibrates the FETCH_SIZE / WRITE_SIZE "
                          "counters against known bytes) and exit")
@@ -485,8 +488,11 @@ def bench_warmstart(a):
     from paper_2507_00156_amd import warmstart as W
 
     h_c, h_f, width = 1 / 32, 1 / 64, 256
-    per_gap = 4
-    gaps, motions = workload.warmstart_dataset(max(1, a.train_solves // per_gap), per_gap, seed=21)
+    if a.ws_design in ("unit", "unit-log"):
+        gaps, motions = workload.warmstart_unit_dataset(max(1, a.train_solves // 12), seed=21,
+                                                         spacing="log" if a.ws_design == "unit-log" else "random")
+    else:
+        gaps, motions = workload.warmstart_dataset(max(1, a.train_solves // 4), 4, seed=21)
     t0 = time.perf_counter()
     Y, its = W.generate(h_f, gaps, motions, tol=1e-6, log=log, keep=lambda g: W.restriction(h_c, h_f, g))
     t_data = time.perf_counter() - t0
@@ -531,6 +537,9 @@ def bench_warmstart(a):
                     "x", len(rows), 0, float(r[:, 4].mean() * 1e3), True, "bf16 (hi/lo) network + f32/f64 solve",
                     "synthetic (two unit spheres, seeded gaps U[0.02,0.2] and N(0,1) rigid motions)",
                     {"workload": f"warm start: {len(gaps)} training solves at h=1/64 kept at the h=1/32 points "
+                                 + {"unit": "(the 12 unit motions at each of uniformly drawn gaps) ",
+                                    "unit-log": "(the 12 unit motions at each of log-spaced gaps) ",
+                                    "random": "(4 random motions at each of uniformly drawn gaps) "}[a.ws_design] +
                                  f"(102420 outputs), width 256, {a.train_steps} Adam steps; {len(rows)} held-out "
                                  "solves at h=1/64 to FP64 residual 1e-8"})
     out["roofline"] = None
