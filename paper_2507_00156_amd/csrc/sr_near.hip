@@ -26,10 +26,11 @@
 // with P_1 = erfcx(t), P_2 = P_1 + (2/sqrt(pi)) t, P_3 = P_2 + (4/(3 sqrt(pi))) t^3.
 // When only the extrapolated values are asked for, the weights w_j are computed first and a pair
 // adds K(S), S_k = sum_j w_j s_k(t_j), to one set of accumulators (the kernels are linear in s_k).
-// Every pair evaluates all three smoothing lengths.  Skipping the lengths whose cut-off ball does not
-// hold the pair saves about 40% of the smoothing work, but it needs pairs sorted into per-class queues
-// so that a batch of 64 shares its class; measured on MI355X, the queue bookkeeping cost more than the
-// smoothing it saved (per-class queues: 27% fewer FP64 FMAs, 19% more VALU instructions in all).
+// A batch of 64 pairs skips a smoothing length when none of its pairs lies within that length's
+// cut-off ball (a wavefront-uniform test).  Skipping per pair would save about 40% of the smoothing
+// work, but it needs pairs sorted into per-class queues so that a batch of 64 shares its class;
+// measured on MI355X, the queue bookkeeping cost more than the smoothing it saved (per-class queues:
+// 27% fewer FP64 FMAs, 19% more VALU instructions in all).
 // Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
 #include <math.h>
 
@@ -454,14 +455,30 @@ __device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Ta
         S1 = T.w[2] * a1;
         S2 = T.w[2] * a2;
         S3 = T.w[2] * a3;
-        smoothing3(r * p.inv_delta[1], E1, p.cutoff, a1, a2, a3);
-        S1 = __builtin_fma(T.w[1], a1, S1);
-        S2 = __builtin_fma(T.w[1], a2, S2);
-        S3 = __builtin_fma(T.w[1], a3, S3);
-        smoothing3(r * p.inv_delta[0], E0, p.cutoff, a1, a2, a3);
-        S1 = __builtin_fma(T.w[0], a1, S1);
-        S2 = __builtin_fma(T.w[0], a2, S2);
-        S3 = __builtin_fma(T.w[0], a3, S3);
+        // the two smaller deltas: when no pair of the wavefront's batch lies within their cut-off ball
+        // (the candidates of a batch come from a few neighbouring cells, so about 40% of the batches
+        // lie beyond cutoff * delta_0) their factors are 1 exactly and the evaluation is skipped
+        const double t1 = r * p.inv_delta[1], t0 = r * p.inv_delta[0];
+        if (__ballot(t1 <= p.cutoff)) {
+            smoothing3(t1, E1, p.cutoff, a1, a2, a3);
+            S1 = __builtin_fma(T.w[1], a1, S1);
+            S2 = __builtin_fma(T.w[1], a2, S2);
+            S3 = __builtin_fma(T.w[1], a3, S3);
+        } else {
+            S1 += T.w[1];
+            S2 += T.w[1];
+            S3 += T.w[1];
+        }
+        if (__ballot(t0 <= p.cutoff)) {
+            smoothing3(t0, E0, p.cutoff, a1, a2, a3);
+            S1 = __builtin_fma(T.w[0], a1, S1);
+            S2 = __builtin_fma(T.w[0], a2, S2);
+            S3 = __builtin_fma(T.w[0], a3, S3);
+        } else {
+            S1 += T.w[0];
+            S2 += T.w[0];
+            S3 += T.w[0];
+        }
     }
     const double ir3 = (ir * ir) * ir;
     if (SL) {
