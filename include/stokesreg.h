@@ -117,14 +117,19 @@ sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
  *   u (m,3)     output single layer (if SR_SL);  v (m,3) output double layer incl. chi q(x0) (if SR_DL).
  *   u_delta, v_delta  optional (may be NULL): (m,3,3) regularized values before extrapolation,
  *               [target][j][component] for delta_j, 1/(8 pi) included, chi q(x0) excluded.
- * m == 0 is a no-op.  SR_ESTATE if the surface, the parameters or a requested density is not set. */
+ * m == 0 is a no-op.  SR_ESTATE if the surface, the parameters or a requested density is not set.
+ * The work is asynchronous on `stream`.  When u_delta and v_delta are NULL and profiling is off,
+ * the near-field kernel runs on a stream the context owns, concurrently with the far field on
+ * `stream`: it starts after the work enqueued on `stream` before the call, and work enqueued on
+ * `stream` after the call starts after it, so the call behaves as one operation on `stream`.  Two
+ * calls on one context must not overlap in time from different host threads. */
 sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const double *x0, const double *n0,
                   const double *b, const double *f0, const double *q0, double *u, double *v,
                   double *u_delta, double *v_delta, void *stream);
 
-/* Per-phase timing.  While profiling is on, every sr_eval records HIP events on its stream around
- * each phase: SR_PHASE_FAR (the far-field sum) and SR_PHASE_NEAR (near regularized sums plus
- * extrapolation).  sr_get_profile waits for the recorded events, writes the accumulated
+/* Per-phase timing.  While profiling is on, every sr_eval runs its phases one after the other on
+ * its stream (not concurrently) and records HIP events around each: SR_PHASE_FAR (the far-field
+ * sum) and SR_PHASE_NEAR (near regularized sums plus extrapolation).  sr_get_profile waits for the recorded events, writes the accumulated
  * milliseconds per phase to ms[0..SR_NPHASES-1] and the number of recorded evaluations to *evals,
  * and clears the record. */
 enum { SR_PHASE_FAR = 0, SR_PHASE_NEAR = 1, SR_NPHASES = 2 };

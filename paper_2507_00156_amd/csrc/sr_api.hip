@@ -130,6 +130,11 @@ struct sr_ctx {
     std::vector<hipEvent_t> ev_pool;     // created events, reused
     std::vector<hipEvent_t> ev_recorded; // 3 per profiled evaluation: start, far done, near done
 
+    // concurrent evaluation: the near-field kernel runs on this stream (default priority,
+    // non-blocking) while the far field runs on the caller's; fork and join events order the two
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
     ~sr_ctx()
     {
         x.release();
@@ -163,6 +168,9 @@ struct sr_ctx {
         t_sort_tmp.release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev_recorded) (void)hipEventDestroy(e);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -579,6 +587,18 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
         nparts = c->tdev.nfront;
     }
     SR_HIP(c->part.reserve((size_t)nparts * 6 * (size_t)m));
+    // Without per-delta outputs and without profiling, the near-field kernel (near sums,
+    // extrapolation, jump term) runs on the side stream concurrently with the far field, and
+    // launch_far_add then adds the far sum on the caller's stream.  Both kernels are bound by vector
+    // ALU issue; the far kernel's few long workgroups leave wave slots free that the near kernel's
+    // fill.  With profiling on, the phases run one after the other so that each has its own time.
+    const bool concurrent = !c->profiling && !u_delta && !v_delta;
+    if (concurrent) {
+        if (!c->side) SR_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        if (!c->ev_fork) SR_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        if (!c->ev_join) SR_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        SR_HIP(hipEventRecord(c->ev_fork, s));
+    }
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     if (tree) {
         // Morton order over the sources' cell grid box, 1024 steps per axis
@@ -595,6 +615,21 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     } else {
         SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, dp.rsharp,
                                  dp.sharp, c->part.p, s));
+    }
+    if (concurrent) {
+        // the side stream starts after everything the caller enqueued before this call (fork) and
+        // the caller's stream continues after the near kernel (join), whatever the launches return
+        hipError_t e0 = hipStreamWaitEvent(c->side, c->ev_fork, 0);
+        hipError_t e1 = e0 == hipSuccess
+                            ? launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p,
+                                                   c->cell_start.p, c->grid, a, dp, nullptr, 0, c->side)
+                            : e0;
+        hipError_t e2 = hipEventRecord(c->ev_join, c->side);
+        hipError_t e3 = hipStreamWaitEvent(s, c->ev_join, 0);
+        for (hipError_t e : {e0, e1, e2, e3})
+            if (e != hipSuccess) return fail(SR_EHIP, "sr_eval: %s", hipGetErrorString(e));
+        SR_HIP(launch_far_add(layers, c->part.p, nparts, a, s));
+        return SR_OK;
     }
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p, c->cell_start.p,

@@ -105,5 +105,7 @@ hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> 
                                 const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,
                                 const CellGrid &grid, const EvalArgs &a, const DevParams &p, const double *part,
                                 int nparts, hipStream_t s);
+// u += far / (8 pi), v += -6 far / (8 pi) for outputs written by launch_near_finalize with nparts = 0
+hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, hipStream_t s);
 
 }  // namespace sr

@@ -842,7 +842,48 @@ hipError_t dispatch(int layers, const SrcRec<double> *rec64, const Pos4<TC> *pos
     return launch_t<TC, false, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
 }
 
+// Far field added to outputs that already hold the near sums, the extrapolation and the jump term
+// (the near kernel run with no far partial sums, concurrently with the far-field kernel).  The
+// extrapolation weights w = e_1^T A^{-1} of eq. (extrap_eqn) satisfy w A = e_1^T and the first column
+// of A is all ones, so they sum to one (up to rounding) and the far sum shared by the three smoothing
+// lengths enters once, unweighted: u += S_far / (8 pi), v += -6 T_far / (8 pi); a target with the
+// modified smoothing has the single weight 1.  One lane per target; the partial sums
+// part[split][channel][target] are read coalesced.
+template <bool SL, bool DL>
+__global__ __launch_bounds__(kBlock) void far_add_kernel(const double *__restrict__ part, int nparts, int64_t m,
+                                                         double *__restrict__ u, double *__restrict__ v)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= m) return;
+    const double inv8pi = 1.0 / (8.0 * kPi);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (SL) {
+            double far = 0.0;
+            for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + i) * (size_t)m + t];
+            u[3 * t + i] += far * inv8pi;
+        }
+        if (DL) {
+            double far = 0.0;
+            for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + 3 + i) * (size_t)m + t];
+            v[3 * t + i] += -6.0 * far * inv8pi;
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)((a.m + kBlock - 1) / kBlock)), block(kBlock);
+    if (layers == (SR_SL | SR_DL))
+        hipLaunchKernelGGL((far_add_kernel<true, true>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+    else if (layers == SR_SL)
+        hipLaunchKernelGGL((far_add_kernel<true, false>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+    else
+        hipLaunchKernelGGL((far_add_kernel<false, true>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+    return hipGetLastError();
+}
 
 hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
                                 const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,

@@ -207,3 +207,55 @@ def test_params_change_rebuilds_index(P, small):
                     cfg["h"], (3.0, 4.0, 5.0))
     assert rel_err(u.cpu().numpy(), ref) <= 1e-10
     ev.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("far", ["direct", "tree"])
+def test_concurrent_phases_equal_serial(P, small, precision, far):
+    # With no per-delta outputs and profiling off, the near-field kernel runs on the context's own
+    # stream concurrently with the far field, and the far sum is added afterwards; with profiling on,
+    # the phases run one after the other and the near kernel adds the far sum itself.  The two differ
+    # only in rounding: (far + near) / (8 pi) against near / (8 pi) + far / (8 pi).  Three
+    # evaluations are enqueued back to back on a non-default stream, each with its densities scaled
+    # by 2^k (exact in every precision) and its outputs copied right after on the same stream: a copy
+    # taken before the near kernel or the far addition finished would differ from 2^k times the
+    # serial result.
+    import torch
+
+    cfg, (u_or, v_or, _, _) = small
+    s, t = cfg["surf"], cfg["targets"]
+    kw = dict(far_method=P.SR_TREE, tree_degree=6, tree_theta=0.6, tree_leaf=64) if far == "tree" else {}
+    ev = P.Evaluator(cfg["h"], cfg["rho"], precision=precision, **kw)
+    ev.set_surface(to_dev(s.x), to_dev(s.normal), to_dev(s.w))
+    f, q, f0, q0 = (to_dev(cfg[k]) for k in ("f", "q", "f0", "q0"))
+    y, x0, n0, b = (to_dev(a) for a in (t.y, t.x0, t.n0, t.b))
+    ev.set_density(P.SR_SL, f)
+    ev.set_density(P.SR_DL, q)
+    torch.cuda.synchronize()
+    P.sr_set_profiling(ev.ctx, True)
+    us, vs = ev.eval(3, y, x0, n0, b, f0, q0)
+    torch.cuda.synchronize()
+    P.sr_set_profiling(ev.ctx, False)
+    P.sr_get_profile(ev.ctx)
+    us, vs = us.cpu().numpy(), vs.cpu().numpy()
+    tol = TOL[precision] if far == "direct" else 1e-3  # the treecode's own error against the direct oracle
+    assert rel_err(us, u_or) <= tol and rel_err(vs, v_or) <= tol
+
+    st = torch.cuda.Stream()
+    snaps, keep = [], []
+    with torch.cuda.stream(st):
+        for k in range(3):
+            c = float(2**k)
+            fk, qk, f0k, q0k = f * c, q * c, f0 * c, q0 * c
+            ev.set_density(P.SR_SL, fk)
+            ev.set_density(P.SR_DL, qk)
+            uk, vk = ev.eval(3, y, x0, n0, b, f0k, q0k)
+            snaps.append((uk.clone(), vk.clone()))
+            keep += [fk, qk, f0k, q0k, uk, vk]
+    torch.cuda.synchronize()
+    ev.close()
+    for k, (uk, vk) in enumerate(snaps):
+        e1 = rel_err(uk.cpu().numpy(), 2**k * us)
+        e2 = rel_err(vk.cpu().numpy(), 2**k * vs)
+        print(f"concurrent {far} prec={precision} k={k}: SL {e1:.2e} DL {e2:.2e}", flush=True)
+        assert e1 <= 1e-13 and e2 <= 1e-13
