@@ -5,8 +5,8 @@
 //
 // Work decomposition (MI355X, 256 CUs in 8 XCDs):
 //   - one lane owns TPL targets; each workgroup (256 lanes) owns 256*TPL targets and one of
-//     kFarSplits contiguous source ranges; blockIdx.x % 8 selects the range, so the round-robin
-//     dispatch over XCDs gives every XCD's L2 a single eighth of the source records;
+//     kFarSplits (16) contiguous source ranges; blockIdx.x % 16 selects the range, so the round-robin
+//     dispatch over the 8 XCDs gives every XCD's L2 two sixteenths of the source records;
 //   - the source index is wavefront-uniform, so each record is fetched once per wavefront through
 //     the scalar data cache and feeds the VALU as scalar operands: no LDS traffic, no barriers;
 //   - near pairs (r^2 <= rc2 by the shared pair_r2 test) are selected out (not multiplied by zero:

@@ -847,35 +847,32 @@ hipError_t dispatch(int layers, const SrcRec<double> *rec64, const Pos4<TC> *pos
 // extrapolation weights w = e_1^T A^{-1} of eq. (extrap_eqn) satisfy w A = e_1^T and the first column
 // of A is all ones, so they sum to one (up to rounding) and the far sum shared by the three smoothing
 // lengths enters once, unweighted: u += S_far / (8 pi), v += -6 T_far / (8 pi); a target with the
-// modified smoothing has the single weight 1.  One lane per target; the partial sums
-// part[split][channel][target] are read coalesced.
+// modified smoothing has the single weight 1.  One lane per (channel, target), channel-major, so
+// that the partial sums part[split][channel][target] are read coalesced and the grid fills the chip.
 template <bool SL, bool DL>
 __global__ __launch_bounds__(kBlock) void far_add_kernel(const double *__restrict__ part, int nparts, int64_t m,
                                                          double *__restrict__ u, double *__restrict__ v)
 {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= m) return;
+    constexpr int c0 = SL ? 0 : 3, nch = (SL ? 3 : 0) + (DL ? 3 : 0);
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nch * m) return;
+    const int c = c0 + (int)(e / m);  // channel 0..2 single layer, 3..5 double layer
+    const int64_t t = e - (int64_t)(c - c0) * m;
+    double far = 0.0;
+    for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + c) * (size_t)m + t];
     const double inv8pi = 1.0 / (8.0 * kPi);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        if (SL) {
-            double far = 0.0;
-            for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + i) * (size_t)m + t];
-            u[3 * t + i] += far * inv8pi;
-        }
-        if (DL) {
-            double far = 0.0;
-            for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + 3 + i) * (size_t)m + t];
-            v[3 * t + i] += -6.0 * far * inv8pi;
-        }
-    }
+    if (c < 3)
+        u[3 * t + c] += far * inv8pi;
+    else
+        v[3 * t + c - 3] += -6.0 * far * inv8pi;
 }
 
 }  // namespace
 
 hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.m + kBlock - 1) / kBlock)), block(kBlock);
+    const int64_t lanes = (layers == (SR_SL | SR_DL) ? 6 : 3) * a.m;
+    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock)), block(kBlock);
     if (layers == (SR_SL | SR_DL))
         hipLaunchKernelGGL((far_add_kernel<true, true>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
     else if (layers == SR_SL)
