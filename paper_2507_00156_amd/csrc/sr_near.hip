@@ -9,8 +9,9 @@
 //        t2 = xh (b ((xh.a)(n0.m) + (n0.a)(xh.m)) - (xh.a)(xh.m)) + n0 b (xh.a)(xh.m),  xh = x - x0
 //   (t1, t2 are the contractions of t^(1)_ijk, t^(2)_ijk with a_j m_k; r^2 - b^2 = |xh|^2 - 2 b xh.n0)
 // with the smoothing factors of eqs. (s1)-(s3) set to 1 for t = r/delta > cutoff (section 3.2).
-// The far-field partial sums are then added (eq. (near_far)) and the three values are combined by
-// the 3x3 extrapolation of eq. (extrap_eqn): u = sum_j w_j u^{delta_j}, w = e_1^T A^{-1} with rows
+// The far-field partial sums are then added (eq. (near_far)): by this kernel, or, when it runs
+// concurrently with the far-field kernel (nparts = 0), afterwards by far_add_kernel.  The three values
+// are combined by the 3x3 extrapolation of eq. (extrap_eqn): u = sum_j w_j u^{delta_j}, w = e_1^T A^{-1} with rows
 // A_j = [1, rho_j I0(lambda_j), rho_j^3 I2(lambda_j)], lambda_j = b/delta_j, by Cramer's rule.
 // If |b| >= cutoff * max delta every pair is beyond the cut-off for every delta, the three values
 // coincide and w = (1, 0, 0) (the matrix is numerically singular there).
