@@ -35,24 +35,32 @@
 // Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
 #include <math.h>
 
+#include <type_traits>
+
 #include "sr_erfcx_table.h"
 #include "sr_internal.h"
 
 namespace sr {
 
-// The erfcx coefficients as a device variable with external linkage: the compiler cannot fold them
+// The erfcx coefficients as device variables with external linkage: the compiler cannot fold them
 // into immediates, so the polynomial reads them with scalar loads into SGPRs instead of keeping 17
-// FP64 constants (34 VGPRs) live across the pair loop.
+// FP64 constants (34 VGPRs) live across the pair loop.  Two tables: degree 16 (|erfc error| ~6e-16)
+// for the double-precision path, degree 11 (~2e-11) for the mixed-precision path, whose
+// single-precision far field (relative error ~1e-7) dominates its error; 5 fewer FMAs per
+// smoothing evaluation and 10 fewer scalar registers.
+template <class EP>
 struct ErfcxCoef {
-    double c[erfcx_poly::kDegree + 1];
+    double c[EP::kDegree + 1];
 };
-constexpr ErfcxCoef make_erfcx_coef()
+template <class EP>
+constexpr ErfcxCoef<EP> make_erfcx_coef()
 {
-    ErfcxCoef r{};
-    for (int k = 0; k <= erfcx_poly::kDegree; ++k) r.c[k] = erfcx_poly::kC[k];
+    ErfcxCoef<EP> r{};
+    for (int k = 0; k <= EP::kDegree; ++k) r.c[k] = EP::kC[k];
     return r;
 }
-__constant__ ErfcxCoef g_erfcx_coef = make_erfcx_coef();
+__constant__ ErfcxCoef<erfcx_poly::Fp64> g_erfcx_coef = make_erfcx_coef<erfcx_poly::Fp64>();
+__constant__ ErfcxCoef<erfcx_poly::Mixed> g_erfcx_coef_mixed = make_erfcx_coef<erfcx_poly::Mixed>();
 
 namespace {
 
@@ -113,23 +121,38 @@ __constant__ constexpr SeriesCoef kSeries = make_series();
 // t < kSeriesT (the
 // pairs closer than kSeriesT delta are added separately by near_pair_series, whose Maclaurin series
 // keep the relative accuracy of s2 ~ t^3 and s3 ~ t^5 that the differences below would lose).
-// erfc(t) = exp(-t^2) erfcx(t), erfcx from the interpolating polynomial of sr_erfcx_table.h (|erfc
-// error| < 1e-15 on [0, 6.25]); beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
-__device__ __forceinline__ void smoothing3(double t, double E, double cutoff, double &s1, double &s2, double &s3)
+// erfcx(t) for 0 <= t <= 6.25 from the interpolating polynomial of sr_erfcx_table.h: the degree-16
+// table, or with LO the mixed-precision path's degree-11 table.
+template <bool LO>
+__device__ __forceinline__ double erfcx_eval(double tc)
 {
-    using namespace erfcx_poly;
-    const double tc = fmin(t, 6.25);
-    const double den = tc + kL;
+    using EP = std::conditional_t<LO, erfcx_poly::Mixed, erfcx_poly::Fp64>;
+    const double den = tc + EP::kL;
     double inv = __builtin_amdgcn_rcp(den);
     double e = __builtin_fma(-den, inv, 1.0);
     inv = __builtin_fma(inv, e, inv);
     e = __builtin_fma(-den, inv, 1.0);
     inv = __builtin_fma(inv, e, inv);
-    const double x = __builtin_fma(kA, (tc - kL) * inv, kB);
-    double pz = g_erfcx_coef.c[kDegree];
+    const double x = __builtin_fma(EP::kA, (tc - EP::kL) * inv, EP::kB);
+    double pz;
+    if constexpr (LO) {
+        pz = g_erfcx_coef_mixed.c[EP::kDegree];
 #pragma unroll
-    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef.c[k]);
-    const double R = kL * inv * pz;
+        for (int k = EP::kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef_mixed.c[k]);
+    } else {
+        pz = g_erfcx_coef.c[EP::kDegree];
+#pragma unroll
+        for (int k = EP::kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef.c[k]);
+    }
+    return EP::kL * inv * pz;
+}
+
+// erfc(t) = exp(-t^2) erfcx(t) (|erfc error| < 1e-15 on [0, 6.25] with the degree-16 table, 2e-11 with
+// LO); beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
+template <bool LO>
+__device__ __forceinline__ void smoothing3(double t, double E, double cutoff, double &s1, double &s2, double &s3)
+{
+    const double R = erfcx_eval<LO>(fmin(t, 6.25));
     const double P2 = __builtin_fma(kTwoOverSqrtPi, t, R);
     const double P3 = __builtin_fma((2.0 / 3.0) * kTwoOverSqrtPi * t * t, t, P2);
     const double Ec = t > cutoff ? 0.0 : E;  // beyond the cut-off s1 = s2 = s3 = 1 exactly
@@ -160,22 +183,11 @@ __device__ __forceinline__ void series3(double t, double &s1, double &s2, double
 //   s1# = 1 - E (R - (c/3)(5t - 2t^3)),  s2# = 1 - E (R + (c/3)(3t - 14t^3 + 4t^5)),
 //   s3# = 1 - E (R + (c/9)(9t + 6t^3 - 4t^5)),  c = 2/sqrt(pi), R = erfcx(t);
 // 1 beyond the cut-off, 0 below kSeriesT (added by the series pass).
+template <bool LO>
 __device__ __forceinline__ void smoothing3_sharp(double t, double cutoff, double &s1, double &s2, double &s3)
 {
-    using namespace erfcx_poly;
     const double E = exp(-t * t);
-    const double tc = fmin(t, 6.25);
-    const double den = tc + kL;
-    double inv = __builtin_amdgcn_rcp(den);
-    double e = __builtin_fma(-den, inv, 1.0);
-    inv = __builtin_fma(inv, e, inv);
-    e = __builtin_fma(-den, inv, 1.0);
-    inv = __builtin_fma(inv, e, inv);
-    const double x = __builtin_fma(kA, (tc - kL) * inv, kB);
-    double pz = g_erfcx_coef.c[kDegree];
-#pragma unroll
-    for (int k = kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef.c[k]);
-    const double R = kL * inv * pz;
+    const double R = erfcx_eval<LO>(fmin(t, 6.25));
     const double t2 = t * t, c3 = kTwoOverSqrtPi / 3.0, c9 = kTwoOverSqrtPi / 9.0;
     const double P1 = R - c3 * t * __builtin_fma(-2.0, t2, 5.0);
     const double P2 = __builtin_fma(c3 * t, __builtin_fma(t2, __builtin_fma(4.0, t2, -14.0), 3.0), R);
@@ -267,14 +279,14 @@ __device__ __forceinline__ void add_delta(double s1, double s2, double s3, doubl
     }
 }
 
-template <int J, bool SL, bool DL, bool COMB>
+template <int J, bool SL, bool DL, bool COMB, bool LO>
 __device__ __forceinline__ void accumulate_delta(double r, double E, double ir, double ir3, double ir5, double dx,
                                                  double dy, double dz, double gx, double gy, double gz, double dg,
                                                  double t1x, double t1y, double t1z, double ex, double ey, double ez,
                                                  const DevParams &p, const Target &T, Acc &A)
 {
     double s1, s2, s3;
-    smoothing3(r * p.inv_delta[J], E, p.cutoff, s1, s2, s3);
+    smoothing3<LO>(r * p.inv_delta[J], E, p.cutoff, s1, s2, s3);
     add_delta<J, SL, DL, COMB>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
                                T.w[J], A);
 }
@@ -299,7 +311,7 @@ __device__ __forceinline__ void series_delta(double r, double ir, double ir3, do
 // One near pair, accumulated at the three smoothing lengths (sorted-delta order).  SER = false: the
 // closed-form smoothing factors, leaving out t < kSeriesT; returns whether some t is below kSeriesT
 // (then the caller calls it again with SER = true, which adds just those terms from the series).
-template <bool SL, bool DL, bool SER, bool P234, bool COMB>
+template <bool SL, bool DL, bool SER, bool P234, bool COMB, bool LO>
 __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
 {
     const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
@@ -370,12 +382,12 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
         const double tb = r * p.inv_delta[0] * (1.0 / 6.0);
         const double B = exp(-tb * tb);
         const double B4 = (B * B) * (B * B), B8 = B4 * B4;
-        accumulate_delta<2, SL, DL, COMB>(r, B8 * B, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
+        accumulate_delta<2, SL, DL, COMB, LO>(r, B8 * B, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
                                     T, A);
         const double B16 = B8 * B8;
-        accumulate_delta<1, SL, DL, COMB>(r, B16, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
+        accumulate_delta<1, SL, DL, COMB, LO>(r, B16, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
                                     T, A);
-        accumulate_delta<0, SL, DL, COMB>(r, (B16 * B16) * B4, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex,
+        accumulate_delta<0, SL, DL, COMB, LO>(r, (B16 * B16) * B4, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex,
                                     ey, ez, p, T, A);
     } else {
 #pragma unroll
@@ -383,13 +395,13 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
             const double tj = r * p.inv_delta[j];
             const double Ej = exp(-tj * tj);
             if (j == 0)
-                accumulate_delta<0, SL, DL, COMB>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                accumulate_delta<0, SL, DL, COMB, LO>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
                                             p, T, A);
             else if (j == 1)
-                accumulate_delta<1, SL, DL, COMB>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                accumulate_delta<1, SL, DL, COMB, LO>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
                                             p, T, A);
             else
-                accumulate_delta<2, SL, DL, COMB>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
+                accumulate_delta<2, SL, DL, COMB, LO>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
                                             p, T, A);
         }
     }
@@ -398,14 +410,14 @@ __device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target 
 
 // A near pair: the closed-form pass, then (rarely) the series pass.  The empty asm hides that the
 // second load reads the same record, so the record is not kept in registers across the first pass.
-template <bool SL, bool DL, bool P234, bool COMB>
+template <bool SL, bool DL, bool P234, bool COMB, bool LO>
 __device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
                                                const DevParams &p, Acc &A)
 {
-    if (near_pair<SL, DL, false, P234, COMB>(rec64[k], T, p, A)) {
+    if (near_pair<SL, DL, false, P234, COMB, LO>(rec64[k], T, p, A)) {
         int kk = k;
         asm volatile("" : "+v"(kk));
-        near_pair<SL, DL, true, P234, COMB>(rec64[kk], T, p, A);
+        near_pair<SL, DL, true, P234, COMB, LO>(rec64[kk], T, p, A);
     }
 }
 
@@ -413,7 +425,7 @@ __device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict_
 // sum_j w_j K(s(t_j)) = K(S) with S_k = sum_j w_j s_k(t_j): the three smoothing lengths share one kernel
 // evaluation and one set of accumulators.  Returns whether t < kSeriesT for some delta (then the
 // series pass adds those terms).
-template <bool SL, bool DL, bool P234>
+template <bool SL, bool DL, bool P234, bool LO>
 __device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
 {
     const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
@@ -452,7 +464,7 @@ __device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Ta
     double S1, S2, S3;
     {
         double a1, a2, a3;
-        smoothing3(r * p.inv_delta[2], E2, p.cutoff, a1, a2, a3);
+        smoothing3<LO>(r * p.inv_delta[2], E2, p.cutoff, a1, a2, a3);
         S1 = T.w[2] * a1;
         S2 = T.w[2] * a2;
         S3 = T.w[2] * a3;
@@ -461,7 +473,7 @@ __device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Ta
         // lie beyond cutoff * delta_0) their factors are 1 exactly and the evaluation is skipped
         const double t1 = r * p.inv_delta[1], t0 = r * p.inv_delta[0];
         if (__ballot(t1 <= p.cutoff)) {
-            smoothing3(t1, E1, p.cutoff, a1, a2, a3);
+            smoothing3<LO>(t1, E1, p.cutoff, a1, a2, a3);
             S1 = __builtin_fma(T.w[1], a1, S1);
             S2 = __builtin_fma(T.w[1], a2, S2);
             S3 = __builtin_fma(T.w[1], a3, S3);
@@ -471,7 +483,7 @@ __device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Ta
             S3 += T.w[1];
         }
         if (__ballot(t0 <= p.cutoff)) {
-            smoothing3(t0, E0, p.cutoff, a1, a2, a3);
+            smoothing3<LO>(t0, E0, p.cutoff, a1, a2, a3);
             S1 = __builtin_fma(T.w[0], a1, S1);
             S2 = __builtin_fma(T.w[0], a2, S2);
             S3 = __builtin_fma(T.w[0], a3, S3);
@@ -520,14 +532,14 @@ __device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Ta
     return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
 }
 
-template <bool SL, bool DL, bool P234>
+template <bool SL, bool DL, bool P234, bool LO>
 __device__ __forceinline__ void near_pair_comb_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
                                                     const DevParams &p, Acc &A)
 {
-    if (near_pair_comb<SL, DL, P234>(rec64[k], T, p, A)) {
+    if (near_pair_comb<SL, DL, P234, LO>(rec64[k], T, p, A)) {
         int kk = k;
         asm volatile("" : "+v"(kk));
-        near_pair<SL, DL, true, P234, true>(rec64[kk], T, p, A);
+        near_pair<SL, DL, true, P234, true, LO>(rec64[kk], T, p, A);
     }
 }
 
@@ -535,7 +547,7 @@ __device__ __forceinline__ void near_pair_comb_full(const SrcRec<double> *__rest
 // (section 2.1): single layer with s1#, s2# (eq. (Sreg)); double layer with the stresslet's 1/r^5
 // replaced by s3#/r^5, accumulated as sum d (d.a)(d.m) s3#/r^5 like the far-field channel.  Sums go to
 // A.sl[0], A.dl[0].  SER as in near_pair.
-template <bool SL, bool DL, bool SER>
+template <bool SL, bool DL, bool SER, bool LO>
 __device__ __forceinline__ bool near_pair_sharp(const SrcRec<double> &s, const Target &T, const DevParams &p,
                                                 Acc &A)
 {
@@ -565,7 +577,7 @@ __device__ __forceinline__ bool near_pair_sharp(const SrcRec<double> &s, const T
     if (SER)
         series3_sharp(t, s1, s2, s3);
     else
-        smoothing3_sharp(t, p.cutoff, s1, s2, s3);
+        smoothing3_sharp<LO>(t, p.cutoff, s1, s2, s3);
     const double ir2 = ir * ir;
     const double ir3 = ir2 * ir;
     if (SL) {
@@ -587,14 +599,14 @@ __device__ __forceinline__ bool near_pair_sharp(const SrcRec<double> &s, const T
     return !SER && t < kSeriesT;
 }
 
-template <bool SL, bool DL>
+template <bool SL, bool DL, bool LO>
 __device__ __forceinline__ void near_pair_sharp_full(const SrcRec<double> *__restrict__ rec64, int k,
                                                      const Target &T, const DevParams &p, Acc &A)
 {
-    if (near_pair_sharp<SL, DL, false>(rec64[k], T, p, A)) {
+    if (near_pair_sharp<SL, DL, false, LO>(rec64[k], T, p, A)) {
         int kk = k;
         asm volatile("" : "+v"(kk));
-        near_pair_sharp<SL, DL, true>(rec64[kk], T, p, A);
+        near_pair_sharp<SL, DL, true, LO>(rec64[kk], T, p, A);
     }
 }
 
@@ -631,16 +643,17 @@ constexpr int depth_for() { return sizeof(TC) == 4 ? 4 : 2; }
 constexpr int kRing = 512;   // per-wave ring buffer of near pairs (power of two >= 63 + depth * 64)
 static_assert(kRing >= kWave - 1 + 4 * kWave && (kRing & (kRing - 1)) == 0, "ring buffer size");
 
-template <bool SL, bool DL, bool SHARP, bool P234, bool COMB>
+// LO: the degree-11 erfcx table of the mixed-precision path
+template <bool SL, bool DL, bool SHARP, bool P234, bool COMB, bool LO>
 __device__ __forceinline__ void eval_pair(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
                                           const DevParams &p, Acc &A)
 {
     if (SHARP)
-        near_pair_sharp_full<SL, DL>(rec64, k, T, p, A);
+        near_pair_sharp_full<SL, DL, LO>(rec64, k, T, p, A);
     else if (COMB)
-        near_pair_comb_full<SL, DL, P234>(rec64, k, T, p, A);
+        near_pair_comb_full<SL, DL, P234, LO>(rec64, k, T, p, A);
     else
-        near_pair_full<SL, DL, P234, false>(rec64, k, T, p, A);
+        near_pair_full<SL, DL, P234, false, LO>(rec64, k, T, p, A);
 }
 
 // COMB (only when no per-delta outputs are asked for): the weights are known before the pair loop and
@@ -652,6 +665,8 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
                                                                EvalArgs a, DevParams p, TC rc2, TC rc2s,
                                                                const double *__restrict__ part, int nparts)
 {
+    // single-precision candidate test = the mixed-precision path: the degree-11 erfcx table
+    constexpr bool kLo = std::is_same<TC, float>::value;
     __shared__ int queue_all[kBlock / kWave][kRing];
     // readfirstlane: tells the compiler the wave index (hence the target) is wavefront-uniform, so the
     // target's data live in scalar registers
@@ -730,13 +745,13 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
                     wave_lds_sync();
                     head = (head + kWave) & (kRing - 1);
                     cnt -= kWave;
-                    eval_pair<SL, DL, SHARP, P234, COMB>(rec64, k2, T, p, A);
+                    eval_pair<SL, DL, SHARP, P234, COMB, kLo>(rec64, k2, T, p, A);
                 }
             }
         }
     }
     wave_lds_sync();
-    if (lane < cnt) eval_pair<SL, DL, SHARP, P234, COMB>(rec64, queue[(head + lane) & (kRing - 1)], T, p, A);
+    if (lane < cnt) eval_pair<SL, DL, SHARP, P234, COMB, kLo>(rec64, queue[(head + lane) & (kRing - 1)], T, p, A);
 
     constexpr int NJ = COMB ? 1 : 3;
 #pragma unroll
