@@ -54,7 +54,7 @@ PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 # HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
 # for the kernel source it was measured on: reported as null once the source's hash differs.
-FAR_TRAFFIC = {"bytes": 9.995e7,
+FAR_TRAFFIC = {"bytes": 1.017e8,
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "3299e8ee0945e4a4517469167f287322deb9d68015fc9cf1964dc4d1e68d81a8",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
