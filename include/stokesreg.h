@@ -82,7 +82,9 @@ typedef struct {
  * tree_degree = 8, tree_theta = 0.7, tree_leaf = 2000. */
 void sr_default_params(sr_params *p);
 
-/* Create a context on HIP device `device` (ordinal).  SR_ENODEV if it does not exist. */
+/* Create a context on HIP device `device` (ordinal).  SR_ENODEV if it does not exist.  The context
+ * owns one non-blocking, default-priority stream and two events on that device (the concurrent
+ * near-field phase of sr_eval), released by sr_destroy; SR_EHIP if they cannot be created. */
 sr_status sr_create(sr_ctx **out, int device);
 
 /* Release the context and all device memory it owns.  NULL is accepted. */

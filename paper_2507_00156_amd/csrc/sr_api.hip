@@ -131,7 +131,8 @@ struct sr_ctx {
     std::vector<hipEvent_t> ev_recorded; // 3 per profiled evaluation: start, far done, near done
 
     // concurrent evaluation: the near-field kernel runs on this stream (default priority,
-    // non-blocking) while the far field runs on the caller's; fork and join events order the two
+    // non-blocking) while the far field runs on the caller's; fork and join events order the two.
+    // Created by sr_create.
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
@@ -399,6 +400,18 @@ sr_status sr_create(sr_ctx **out, int device)
     if (!c) return fail(SR_ENOMEM, "sr_create: out of host memory");
     c->device = device;
     sr_default_params(&c->prm);
+    {
+        // the near-field stream of the concurrent evaluation and its fork and join events
+        DeviceGuard g(device);
+        hipError_t e = g.ok ? hipSuccess : hipErrorInvalidDevice;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(SR_EHIP, "sr_create: stream or event creation failed: %s", hipGetErrorString(e));
+        }
+    }
     *out = c;
     return SR_OK;
 }
@@ -590,15 +603,11 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     // Without per-delta outputs and without profiling, the near-field kernel (near sums,
     // extrapolation, jump term) runs on the side stream concurrently with the far field, and
     // launch_far_add then adds the far sum on the caller's stream.  Both kernels are bound by vector
-    // ALU issue; the far kernel's few long workgroups leave wave slots free that the near kernel's
-    // fill.  With profiling on, the phases run one after the other so that each has its own time.
+    // ALU issue but stall differently, and the near kernel's short one-target wavefronts fill the
+    // issue cycles and the wave slots the far kernel leaves (8.5% less time at the 42k-source
+    // ellipsoid).  With profiling on, the phases run one after the other so that each has its own time.
     const bool concurrent = !c->profiling && !u_delta && !v_delta;
-    if (concurrent) {
-        if (!c->side) SR_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        if (!c->ev_fork) SR_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        if (!c->ev_join) SR_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        SR_HIP(hipEventRecord(c->ev_fork, s));
-    }
+    if (concurrent) SR_HIP(hipEventRecord(c->ev_fork, s));
     if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
     if (tree) {
         // Morton order over the sources' cell grid box, 1024 steps per axis
