@@ -10,7 +10,9 @@
 
 namespace sr {
 
-constexpr int kAnterpChunk = 2048;  // points per anterpolation work item
+// Points per anterpolation work item: small enough that the two-sphere problem (68k points per
+// sphere, three tree levels) gives about 900 workgroups for the 256 CUs (2048 gave about 140).
+constexpr int kAnterpChunk = 256;
 
 // One cluster: bounding box, squared radius r_c^2 = (1/4) |hi - lo|^2, points [begin, end) of the
 // tree-ordered sources, children [first_child, first_child + nchild) (nchild = 0 for a leaf).

@@ -215,7 +215,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxDeg = 16;
 constexpr int kSub = 64;         // points per LDS sub-chunk
-constexpr int kTilesPerWave = 12;  // 16-proxy tiles per wavefront and pass
+constexpr int kTilesPerWave = 6;  // 16-proxy tiles per wavefront and pass: degree 6 (22 tiles) keeps all
+                                  // four wavefronts busy in one pass, degree 8 (46 tiles) takes two
 
 // barycentric Lagrange basis at v for the Chebyshev points of [lo, hi] (the oracle's rules)
 __device__ void lagrange_1d(double v, double lo, double hi, int p, const double *cosk, double *L)
@@ -283,9 +284,11 @@ __global__ __launch_bounds__(kBlock) void anterp_kernel(AnterpArgs a)
     for (int sub = b0; sub < b1; sub += kSub) {
         const int t = (int)threadIdx.x;
         if (t < 3 * kSub) {
+            // the basis goes straight to its LDS row (a local array indexed by the run-time degree
+            // would live in scratch memory)
             const int pt = t / 3, ax = t % 3;
             const int gi = sub + pt;
-            double L[kMaxDeg + 1];
+            double *L = basis[pt][ax];
             if (gi < b1) {
                 const SrcRec<double> &s = a.trec[gi];
                 const double v = ax == 0 ? s.x : (ax == 1 ? s.y : s.z);
@@ -293,7 +296,6 @@ __global__ __launch_bounds__(kBlock) void anterp_kernel(AnterpArgs a)
             } else {
                 for (int k = 0; k <= p; ++k) L[k] = 0.0;
             }
-            for (int k = 0; k <= p; ++k) basis[pt][ax][k] = L[k];
         } else {
             const int pt = t - 3 * kSub;
             const int gi = sub + pt;
@@ -345,31 +347,35 @@ __global__ __launch_bounds__(kBlock) void anterp_kernel(AnterpArgs a)
     }
 }
 
-// sum the partial products of each cluster's items (in item order) into its proxy records
+// sum the partial products of each cluster's items (in item order) into its proxy records; one lane
+// per (cluster, proxy, channel), so that a cluster with many items (the root) is not one thread's
+// serial loop, with 8 items' loads in flight; the additions keep the item order
 __global__ __launch_bounds__(kBlock) void anterp_reduce_kernel(const int *node_item0, const double *partial,
                                                                 int nnodes, int nprox, ProxRec<double> *prox64,
                                                                 ProxRec<float> *prox32)
 {
+    constexpr int kInFlight = 8;
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t total = (int64_t)nnodes * nprox;
+    const int64_t total = (int64_t)nnodes * nprox * 16;
     if (gid >= total) return;
-    const int node = (int)(gid / nprox);
-    const int P = (int)(gid % nprox);
-    double s[15];
+    const int c = (int)(gid % 16);
+    if (c == 15) return;  // padding channel of the partial products
+    const int64_t np = gid / 16;  // node * nprox + P
+    const int node = (int)(np / nprox);
+    const int P = (int)(np % nprox);
+    const int i1 = node_item0[node + 1];
+    double s = 0.0;
+    int it = node_item0[node];
+    for (; it + kInFlight <= i1; it += kInFlight) {
+        double v[kInFlight];
 #pragma unroll
-    for (int c = 0; c < 15; ++c) s[c] = 0.0;
-    for (int it = node_item0[node]; it < node_item0[node + 1]; ++it) {
-        const double *src = partial + ((size_t)it * nprox + P) * 16;
+        for (int u = 0; u < kInFlight; ++u) v[u] = partial[((size_t)(it + u) * nprox + P) * 16 + c];
 #pragma unroll
-        for (int c = 0; c < 15; ++c) s[c] += src[c];
+        for (int u = 0; u < kInFlight; ++u) s += v[u];
     }
-    ProxRec<double> &r = prox64[gid];
-    ProxRec<float> &h = prox32[gid];
-#pragma unroll
-    for (int c = 0; c < 15; ++c) {
-        r.g[c] = s[c];
-        h.g[c] = (float)s[c];
-    }
+    for (; it < i1; ++it) s += partial[((size_t)it * nprox + P) * 16 + c];
+    prox64[np].g[c] = s;
+    prox32[np].g[c] = (float)s;
 }
 
 // ---- target ordering ----
@@ -649,7 +655,7 @@ hipError_t launch_anterp(const TreeDev &D, const double *cosk, double *partial, 
     hipLaunchKernelGGL(anterp_kernel, dim3(D.nitems, passes), dim3(kBlock), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t total = (int64_t)D.nnodes * D.nprox;
+    const int64_t total = (int64_t)D.nnodes * D.nprox * 16;
     hipLaunchKernelGGL(anterp_reduce_kernel, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        D.node_item0, partial, D.nnodes, D.nprox, D.prox64, D.prox32);
     return hipGetLastError();
