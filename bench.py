@@ -3,11 +3,16 @@
 Workload (one step = one call evaluating u and v at all targets, densities resident in HBM):
 ellipsoid semi-axes (1, 0.8, 0.6), h = 1/64 grid-line quadrature (N = 42342 points), targets = all
 quadrature points + 20000 points within +-3h of the surface (M = 62342), rho = (2, 3, 4), cut-off 6,
-direct far field.  The headline runs the mixed path (far field FP32 with FP64 accumulation, near
-field and extrapolation FP64); the FP64 path is reported beside it.
+direct far field.  The headline runs the FP64 path (every sum in double precision, as the paper's
+code); the mixed path (far field FP32 with FP64 accumulation, near field and extrapolation FP64) is
+reported beside it.
 
 Prints ONE JSON line.  Metric: target-source interactions per second = 2 M N / t (each target-source
-pair counted once for the single layer and once for the double layer per extrapolated evaluation).
+pair counted once for the single layer and once for the double layer per extrapolated evaluation),
+with the seconds per SL+DL evaluation, single-layer-only and double-layer-only rates, the maximum and
+L2 relative errors of both paths against the FP64 oracle on the oracle's timed sample of targets, and
+the GMRES iterations and seconds of the two-sphere solve (zero start, FP64 relative residual 1e-8) at
+gaps 0.1, 0.05, 0.02.
 
 Other workloads (--workload; each prints its own JSON line):
   tree       ellipsoid (1, 0.8, 0.6), h = 1/128 (N = 169342, M = 189342), treecode far field (degree 8,
@@ -25,6 +30,7 @@ Other workloads (--workload; each prints its own JSON line):
              error against the FP64 direct sum.
   drops      the paper's two drops nearly touching (section 4.3): GMRES to 1e-10 at h = 1/16 ... 1/128,
              iterations, times and the self-convergence errors of Table 2.
+  peak       vector-ALU issue rates of the GPU (FP32 FMA unpacked, FP64 FMA, FP32 rsq).
 """
 from __future__ import annotations
 
@@ -40,38 +46,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic work of one far-field pair in the combined single+double layer pass (FMA = 2 flops,
-# the reciprocal square root counted as 1): d = y - x (3), r^2 (5), rsqrt (1), r^-2 and r^-3 (2),
-# single layer g = fw - c nw (6), d.g (5), scale (1), accumulate g/r + d s (12); double layer
-# a = q - q0 (3), d.a (5), d.m (5), r^-5 (1), coefficient (2), accumulate (6).
-FAR_FLOPS_PER_PAIR_SLDL = 57
-# Per-lane VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  Packed FP32 is not
-# used by this build, so FP32 and FP64 FMAs issue at the same rate.
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6
+# Algorithmic work per far-field pair, per layer (FMA = 2 flops; the reciprocal square root counted
+# separately): single layer 34 = d = y - x (3), r^2 (5), r^-2 and r^-3 (2), g = fw - c nw (6), d.g (5),
+# scale (1), accumulate g/r + d (d.g)/r^3 (12); double layer 32 = d (3), r^2 (5), r^-2, r^-3, r^-5 (3),
+# a = q - q0 (3), d.a (5), d.m (5), coefficient (2), accumulate (6).  An SL+DL evaluation is one SL pair
+# and one DL pair per far target-source pair: 66 flops.
+FAR_FLOPS_SL, FAR_FLOPS_DL = 34, 32
+FAR_FLOPS_PER_PAIR_SLDL = FAR_FLOPS_SL + FAR_FLOPS_DL
+# MI355X published peaks (AMD): FP64 vector 78.6 TFLOP/s, FP32 vector 157.3 TFLOP/s (the latter with two
+# FP32 operations per lane and cycle, i.e. packed FP32, which this build does not use); the attainable
+# unpacked FP32 rate is measured by --workload peak and reported beside.
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_PUBLISHED_TFLOPS = 157.3
+PEAK_VALU_TFLOPS = PEAK_FP64_TFLOPS
 TREE_FLOPS_PER_PROXY_PAIR = 75  # SL 24 + DL 40 + d, r^2, rsqrt, 1/r^2, 1/r^3 (11); FMA = 2
-PEAK_FP32_PUBLISHED_TFLOPS = 157.3  # with packed FP32 (dual-issue per lane)
 
-# HBM bytes per launch of the mixed far-field kernel at this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).  Valid only
-# for the kernel source it was measured on: reported as null once the source's hash differs.
-FAR_TRAFFIC = {"bytes": 1.017e8,
+# HBM bytes per launch of the far-field kernels at this workload (FP64 and mixed), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).
+# Valid only for the kernel sources they were measured on: reported as null once a source's hash differs.
+FAR_TRAFFIC = {"bytes": {"fp64": 1.066e8, "mixed": 1.018e8},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
-                           "3299e8ee0945e4a4517469167f287322deb9d68015fc9cf1964dc4d1e68d81a8",
+                           "54c490788c6d13c1bddc22e0c0d0bffb6743d877a57c73a5e3f9b3f09f5fb7d2",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "de49c94daa5b787bcf3b75d1d18f36da669177a1c1f9d55b0213853b294010eb"}}
+                           "bd3ae02a39b7ba0fb5045799ae84db7f813ef252c3e3dcb545d48627b06f0837"}}
 
 
-def far_traffic():
+def far_traffic(precision):
     import hashlib
 
     for rel, digest in FAR_TRAFFIC["sources"].items():
         try:
             with open(os.path.join(ROOT, rel), "rb") as f:
-                if hashlib.sha256(f.read()).hexdigest() != digest:
+                if digest is None or hashlib.sha256(f.read()).hexdigest() != digest:
                     return None
         except OSError:
             return None
-    return FAR_TRAFFIC["bytes"]
+    return FAR_TRAFFIC["bytes"][precision]
 
 
 def parse():
@@ -81,9 +91,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle baseline")
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--workload", choices=["c2", "tree", "gmres", "mlp", "warmstart", "table1", "sweep", "drops"],
-                    default="c2")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="fp64", help="c2: the headline path")
+    ap.add_argument("--workload", choices=["c2", "tree", "gmres", "mlp", "warmstart", "table1", "sweep", "drops",
+                                           "peak"], default="c2")
+    ap.add_argument("--no-gmres", action="store_true", help="c2: leave out the two-sphere GMRES solves")
     ap.add_argument("--drops-max", type=int, default=128, help="drops: finest 1/h")
     ap.add_argument("--train-solves", type=int, default=792, help="warmstart: training solves")
     ap.add_argument("--train-steps", type=int, default=500000, help="warmstart: optimizer steps")
@@ -149,8 +160,9 @@ def time_eval(P, ev, args_dev, steps, warmup, profile):
 
 
 def cpu_baseline(cfg, target_seconds):
-    """The FP64 oracle (three full regularized sums per target, then the 3x3 solve) on a bounded,
-    evenly spaced sample of the same targets; scaled to interactions/s."""
+    """The FP64 oracle (three full regularized sums per target, then the 3x3 solve) on all host threads,
+    on a bounded, evenly spaced sample of the same targets; scaled to interactions/s.  Returns the
+    baseline record, the sample's indices and the oracle's (u, v) there."""
     import oracle
 
     t = cfg["targets"]
@@ -165,12 +177,73 @@ def cpu_baseline(cfg, target_seconds):
     k = int(np.clip(k0 * target_seconds / max(dt, 1e-3), k0, t.m))
     idx = np.linspace(0, t.m - 1, k).astype(np.int64)
     t0 = time.perf_counter()
-    oracle.sl_cfg(cfg, idx)
-    oracle.dl_cfg(cfg, idx)
+    uo = oracle.sl_cfg(cfg, idx)
+    vo = oracle.dl_cfg(cfg, idx)
     dt = time.perf_counter() - t0
-    return {"value": 2.0 * k * n / dt, "unit": "interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s",
-            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    rec = {"value": 2.0 * k * n / dt, "unit": "interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    return rec, idx, (uo, vo)
+
+
+def cpu_baseline_1thread(cfg, target_seconds):
+    """The oracle on one thread, on a smaller evenly spaced sample."""
+    import oracle
+
+    t, n = cfg["targets"], cfg["surf"].n
+    nt = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        k0 = 16
+        idx = np.linspace(0, t.m - 1, k0).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.sl_cfg(cfg, idx)
+        oracle.dl_cfg(cfg, idx)
+        dt = time.perf_counter() - t0
+        k = int(np.clip(k0 * target_seconds / max(dt, 1e-3), k0, t.m))
+        idx = np.linspace(0, t.m - 1, k).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.sl_cfg(cfg, idx)
+        oracle.dl_cfg(cfg, idx)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(nt)
+    return {"value": 2.0 * k * n / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s, one thread",
+            "cpu_model": cpu_model()}
+
+
+def cpu_localized_baseline(cfg, target_seconds, gpu_fp64):
+    """The paper-style localized CPU evaluation (far pairs once, near pairs at three deltas; gcc -O2,
+    OpenMP over targets) on all host threads and on one, on evenly spaced samples; its error against the
+    GPU FP64 result is reported for information (it is not a checker)."""
+    import cpu_localized as L
+
+    t, n = cfg["targets"], cfg["surf"].n
+    out = {"kind": "paper-style localized CPU evaluation (not the oracle)", "unit": "interactions/s",
+           "cpu_model": cpu_model()}
+    nt = L.num_threads()
+    for label, threads in (("all_threads", nt), ("one_thread", 1)):
+        L.set_num_threads(threads)
+        try:
+            k0 = 512 if threads > 1 else 64
+            idx = np.linspace(0, t.m - 1, k0).astype(np.int64)
+            t0 = time.perf_counter()
+            L.evaluate(cfg, idx)
+            dt = time.perf_counter() - t0
+            k = int(np.clip(k0 * (target_seconds / 2) / max(dt, 1e-3), k0, t.m))
+            idx = np.linspace(0, t.m - 1, k).astype(np.int64)
+            t0 = time.perf_counter()
+            u, v = L.evaluate(cfg, idx)
+            dt = time.perf_counter() - t0
+        finally:
+            L.set_num_threads(nt)
+        out[label] = {"value": 2.0 * k * n / dt, "cores": threads,
+                      "sample": f"{k} of {t.m} targets (evenly spaced), single+double layer, {dt:.1f} s"}
+        if label == "all_threads":
+            out["max_rel_diff_vs_gpu_fp64"] = {"sl": errors_vs(u, gpu_fp64[0][idx])["max_rel"],
+                                                "dl": errors_vs(v, gpu_fp64[1][idx])["max_rel"]}
+    return out
 
 
 def cpu_baseline_tree(cfg, target_seconds, p=8, theta=0.7, leaf=2000):
@@ -716,6 +789,195 @@ def bench_drops(a):
     print(json.dumps(out), flush=True)
 
 
+def near_pair_count(cfg):
+    """Target-source pairs within the near radius cutoff * max delta (FP64 distances), for the far-pair
+    count of the roofline: far pairs = M N - this."""
+    from scipy.spatial import cKDTree
+
+    s, t = cfg["surf"], cfg["targets"]
+    rnear = 6.0 * max(cfg["rho"]) * cfg["h"]
+    return int(cKDTree(s.x).query_ball_point(t.y, rnear, return_length=True).sum())
+
+
+def peak_rates():
+    """Measured vector-ALU rates from bench_peak.so (TFLOP/s, an FMA counting 2; rsq and add in Tops/s):
+    unpacked FP32 FMA (scalar and vector operands), FP64 FMA, FP32 rsq, FP32 and FP64 add; 2048
+    workgroups of 256 lanes, best of 4 launches."""
+    import ctypes as C
+
+    path = os.path.join(ROOT, "bench_peak.so")
+    if not os.path.exists(path):
+        return None
+    L = C.CDLL(path)
+    L.pk_run.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float)]
+    L.pk_run.restype = C.c_double
+    out = {}
+    for kind, name, iters in ((0, "fp32_fma_unpacked", 4096), (1, "fp64_fma", 2048), (2, "fp32_rsq", 2048),
+                              (3, "fp32_add", 4096), (4, "fp32_fma_unpacked_vector_operands", 4096),
+                              (5, "fp64_add", 2048)):
+        best = 0.0
+        for _ in range(4):
+            ms = C.c_float()
+            ops = L.pk_run(kind, iters, 2048, C.byref(ms))
+            if ops < 0:
+                return None
+            best = max(best, ops / (ms.value / 1e3) / 1e12)
+        out[name] = best
+    return out
+
+
+def bench_peak(a):
+    r = peak_rates()
+    out = base_line("vector ALU issue rate (microbenchmark)", r["fp32_fma_unpacked"], "TFLOP/s", 4, 0, None, True,
+                    "f32", "synthetic (register-resident FMA / rsq chains)",
+                    {"workload": "2048 workgroups x 256 lanes, 16 independent chains per lane"})
+    out["roofline"] = None
+    out["rates"] = r
+    out["published"] = {"fp64_vector": PEAK_FP64_TFLOPS, "fp32_vector_packed": PEAK_FP32_PUBLISHED_TFLOPS}
+    print(json.dumps(out), flush=True)
+
+
+def errors_vs(got, ref):
+    """Max and L2 relative errors (Euclidean norm per target) of got against ref."""
+    d = np.linalg.norm(got - ref, axis=1)
+    nr = np.linalg.norm(ref, axis=1)
+    return {"max_rel": float(d.max() / nr.max()), "l2_rel": float(np.sqrt((d ** 2).sum() / (nr ** 2).sum()))}
+
+
+def gmres_summary(log_prefix="[bench]"):
+    """Two spheres at h = 1/64, gaps 0.1, 0.05, 0.02, one seeded rigid motion per gap: refined GMRES from
+    zero to an FP64 relative residual of 1e-8 (inner operator mixed with the treecode far field, degree 6,
+    theta 0.6, leaf 4000; outer residuals FP64 with the direct far field); iterations and seconds."""
+    import torch
+
+    import workload
+    from paper_2507_00156_amd import warmstart as W
+
+    h = 1 / 64
+    tree_kw = dict(far_method=1, tree_degree=6, tree_theta=0.6, tree_leaf=4000)
+    per_gap = {}
+    for gap in (0.1, 0.05, 0.02):
+        sysm = W.TwoSpheres(h, gap, precision=1, **tree_kw)
+        motion = workload.rigid_motion(np.random.default_rng(int(round(gap * 1000))))
+        b = sysm.R.rhs(motion)
+        sysm.R.solve_refined(b, tol=1e-8, restart=100)  # set-up: trees, FP64 evaluators (untimed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, nout, rr = sysm.R.solve_refined(b, tol=1e-8, restart=100)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        per_gap[str(gap)] = {"gmres_iterations": it, "fp64_corrections": nout, "fp64_relres": rr, "seconds": dt}
+        log(f"{log_prefix} gmres gap {gap}: {it} iterations, {nout} FP64 corrections, residual {rr:.1e}, {dt:.2f} s")
+        sysm.close()
+    return per_gap
+
+
+def bench_c2(a):
+    import torch
+
+    import paper_2507_00156_amd as P
+    import workload
+
+    cfg = workload.build_config("c2")
+    s, t = cfg["surf"], cfg["targets"]
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()  # noqa: E731
+    args_dev = [dev(t.y), dev(t.x0), dev(t.n0), dev(t.b), dev(cfg["f0"]), dev(cfg["q0"])]
+    N, M = s.n, t.m
+    res, setup, outs = {}, {}, {}
+    for prec_name, prec in (("fp64", P.SR_FP64), ("mixed", P.SR_MIXED)):
+        ev = P.Evaluator(cfg["h"], cfg["rho"], precision=prec)
+        xs, ns, ws, fd, qd = dev(s.x), dev(s.normal), dev(s.w), dev(cfg["f"]), dev(cfg["q"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev.set_surface(xs, ns, ws)  # geometry ingest (copies, host spatial index)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ev.set_density(P.SR_SL, fd)
+        ev.set_density(P.SR_DL, qd)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ev.eval(P.SR_SL | P.SR_DL, *args_dev)  # first evaluation: cell list, packed records, then the sums
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        setup[prec_name] = {"set_surface_ms": 1e3 * (t1 - t0), "set_density_ms": 1e3 * (t2 - t1),
+                            "first_eval_ms": 1e3 * (t3 - t2)}
+        steps = a.steps if prec_name == a.precision else max(3, a.steps // 2)
+        ms, wall, phases, out, serial_ms = time_eval(P, ev, args_dev, steps, a.warmup, profile=True)
+        outs[prec_name] = (out[0].cpu().numpy(), out[1].cpu().numpy())
+        # each layer alone (same targets, the other layer's work left out)
+        one = {}
+        for name, lay in (("sl", P.SR_SL), ("dl", P.SR_DL)):
+            o = ev.eval(lay, *args_dev)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            k = max(3, steps // 2)
+            e0.record()
+            for _ in range(k):
+                ev.eval(lay, *args_dev, out=(o[0], o[1], None, None))
+            e1.record()
+            torch.cuda.synchronize()
+            one[name] = e0.elapsed_time(e1) / k
+        ev.check()
+        res[prec_name] = dict(ms=ms, wall=wall, phases=phases, steps=steps, serial_ms=serial_ms, sl_ms=one["sl"],
+                              dl_ms=one["dl"])
+        log(f"[bench] {prec_name}: {ms:.3f} ms/step (phases one after the other: {serial_ms:.3f} ms, far "
+            f"{phases[0]:.3f} ms, near+extrap {phases[1]:.3f} ms); SL alone {one['sl']:.3f} ms, DL alone "
+            f"{one['dl']:.3f} ms")
+        ev.close()
+
+    near_pairs = near_pair_count(cfg)
+    far_pairs = M * N - near_pairs
+    peaks = peak_rates()
+
+    def roofline(prec_name, peak, peak_name):
+        far_ms = res[prec_name]["phases"][0]
+        achieved = FAR_FLOPS_PER_PAIR_SLDL * far_pairs / (far_ms / 1e3) / 1e12
+        return {"bound": "alu", "kernel": f"far_direct_kernel<{'double' if prec_name == 'fp64' else 'float'}> "
+                "(far-field pair sum, single+double layer)", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "peak_is": peak_name, "traffic": far_traffic(prec_name),
+                "traffic_unit": "bytes per launch (HBM, counters scaled by a copy calibration)",
+                "flops_per_pair": FAR_FLOPS_PER_PAIR_SLDL, "far_pairs_per_launch": far_pairs,
+                "near_pairs_per_launch": near_pairs, "kernel_ms": far_ms,
+                "kernel_ms_from": "second pass of this run with profiling on: the phases run one after the other "
+                                  "and HIP events on the evaluation stream time each; the timed steps run the far "
+                                  "and near kernels concurrently"}
+
+    head = res[a.precision]
+    ms = head["ms"]
+    out = base_line("target-source interactions/s (extrapolated single+double layer evaluation)", 2.0 * M * N / (ms / 1e3),
+                    "interactions/s", head["steps"], a.warmup, ms, True, "f64" if a.precision == "fp64" else "f32+f64",
+                    "synthetic (seeded ellipsoid quadrature, degree-4 harmonic densities, near targets)",
+                    {"workload": "ellipsoid (1,0.8,0.6), h=1/64: N=42342 sources, M=62342 targets "
+                                 "(42342 on-surface + 20000 within 3h), single+double layer, rho=(2,3,4), cutoff 6, "
+                                 "direct far field", "precision": a.precision, "n_sources": N, "n_targets": M,
+                     "s_per_sl_dl_eval": ms / 1e3})
+    out["roofline"] = (roofline("fp64", PEAK_FP64_TFLOPS, "published FP64 vector") if a.precision == "fp64"
+                       else roofline("mixed", PEAK_FP32_PUBLISHED_TFLOPS, "published FP32 vector (packed)"))
+    for name, r in res.items():
+        out[name] = {"ms_per_step": r["ms"], "interactions_per_s": 2.0 * M * N / (r["ms"] / 1e3),
+                     "s_per_sl_dl_eval": r["ms"] / 1e3, "sl_only_ms": r["sl_ms"], "dl_only_ms": r["dl_ms"],
+                     "sl_interactions_per_s": M * N / (r["sl_ms"] / 1e3),
+                     "dl_interactions_per_s": M * N / (r["dl_ms"] / 1e3),
+                     "far_ms": r["phases"][0], "near_extrap_ms": r["phases"][1],
+                     "ms_per_step_phases_serial": r["serial_ms"], "setup_ms": setup[name]}
+    mixed_rf = roofline("mixed", PEAK_FP32_PUBLISHED_TFLOPS, "published FP32 vector (packed)")
+    if peaks:
+        mixed_rf["frac_of_measured_unpacked_fp32"] = mixed_rf["achieved"] / peaks["fp32_fma_unpacked"]
+    out["mixed"]["roofline"] = mixed_rf
+    out["vector_alu_measured_tflops"] = peaks
+    if not a.no_gmres:
+        out["gmres_two_spheres_h64"] = gmres_summary()
+    if not a.no_cpu_baseline:
+        cb, idx, (uo, vo) = cpu_baseline(cfg, a.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["error_vs_oracle"] = {"sample": cb["sample"]}
+        for name, (u, v) in outs.items():
+            out["error_vs_oracle"][name] = {"sl": errors_vs(u[idx], uo), "dl": errors_vs(v[idx], vo)}
+        out["cpu_baseline_1thread"] = cpu_baseline_1thread(cfg, a.cpu_seconds / 2)
+        out["cpu_localized"] = cpu_localized_baseline(cfg, a.cpu_seconds / 2, outs["fp64"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -733,100 +995,15 @@ def main():
 
         P.load_library()
         {"tree": bench_tree, "gmres": bench_gmres, "mlp": bench_mlp, "warmstart": bench_warmstart,
-         "table1": bench_table1, "sweep": bench_sweep, "drops": bench_drops}[a.workload](a)
+         "table1": bench_table1, "sweep": bench_sweep, "drops": bench_drops, "peak": bench_peak}[a.workload](a)
         return
     import torch
 
+    torch.cuda.init()
     import paper_2507_00156_amd as P
-    import workload
 
-    cfg = workload.build_config("c2")
-    s, t = cfg["surf"], cfg["targets"]
-    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()  # noqa: E731
-    args_dev = [dev(t.y), dev(t.x0), dev(t.n0), dev(t.b), dev(cfg["f0"]), dev(cfg["q0"])]
-    N, M = s.n, t.m
-    res = {}
-    setup = {}
-    for prec_name, prec in (("mixed", P.SR_MIXED), ("fp64", P.SR_FP64)):
-        ev = P.Evaluator(cfg["h"], cfg["rho"], precision=prec)
-        xs, ns, ws, fd, qd = dev(s.x), dev(s.normal), dev(s.w), dev(cfg["f"]), dev(cfg["q"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev.set_surface(xs, ns, ws)  # geometry ingest (copies, host spatial index)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ev.set_density(P.SR_SL, fd)
-        ev.set_density(P.SR_DL, qd)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        ev.eval(P.SR_SL | P.SR_DL, *args_dev)  # first evaluation: cell list, packed records, then the sums
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        if prec_name == a.precision:
-            setup = {"set_surface_ms": 1e3 * (t1 - t0), "set_density_ms": 1e3 * (t2 - t1),
-                     "first_eval_ms": 1e3 * (t3 - t2)}
-        steps = a.steps if prec_name == a.precision else max(3, a.steps // 4)
-        ms, wall, phases, _, serial_ms = time_eval(P, ev, args_dev, steps, a.warmup, profile=True)
-        res[prec_name] = dict(ms=ms, wall=wall, phases=phases, steps=steps, serial_ms=serial_ms)
-        print(f"[bench] {prec_name}: {ms:.3f} ms/step (phases one after the other: {serial_ms:.3f} ms, far "
-              f"{phases[0]:.3f} ms, near+extrap {phases[1]:.3f} ms)", file=sys.stderr, flush=True)
-        ev.close()
-
-    head = res[a.precision]
-    ms = head["ms"]
-    value = 2.0 * M * N / (ms / 1e3)
-    far_ms = head["phases"][0]
-    achieved = FAR_FLOPS_PER_PAIR_SLDL * M * N / (far_ms / 1e3) / 1e12
-    out = {
-        "metric": "target-source interactions/s (extrapolated single+double layer evaluation)",
-        "value": value,
-        "unit": "interactions/s",
-        "n_gpus": 1,
-        "steps": head["steps"],
-        "warmup": a.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
-        "data": "synthetic (seeded ellipsoid quadrature, degree-4 harmonic densities, near targets)",
-        "config": {
-            "workload": "ellipsoid (1,0.8,0.6), h=1/64: N=42342 sources, M=62342 targets "
-                        "(42342 on-surface + 20000 within 3h), single+double layer, rho=(2,3,4), cutoff 6, "
-                        "direct far field",
-            "precision": a.precision,
-            "n_sources": N,
-            "n_targets": M,
-            "s_per_sl_dl_eval": ms / 1e3,
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "far_direct_kernel (far-field pair sum)",
-            "achieved": achieved,
-            "peak": PEAK_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_VALU_TFLOPS,
-            "traffic": far_traffic() if a.precision == "mixed" else None,
-            "traffic_unit": "bytes per launch (HBM, counters scaled by a copy calibration)",
-            "flops_per_pair": FAR_FLOPS_PER_PAIR_SLDL,
-            "pairs_per_launch": M * N,
-            "kernel_ms": far_ms,
-            "kernel_ms_from": "second pass of this run with profiling on: the phases run one after the other and "
-                              "HIP events on the evaluation stream time each; the timed steps run the far and near "
-                              "kernels concurrently",
-            "frac_of_packed_fp32_published": achieved / PEAK_FP32_PUBLISHED_TFLOPS,
-        },
-        "phases_ms": {"far": far_ms, "near_extrap": head["phases"][1],
-                      "ms_per_step_phases_serial": head["serial_ms"]},
-        "other_precision": {k: {"ms_per_step": v["ms"], "value": 2.0 * M * N / (v["ms"] / 1e3),
-                                "far_ms": v["phases"][0], "near_ms": v["phases"][1],
-                                "ms_per_step_phases_serial": v["serial_ms"]}
-                            for k, v in res.items() if k != a.precision},
-    }
-    out["setup_ms"] = setup  # one-time: not part of the timed steps
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, a.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    P.load_library()
+    bench_c2(a)
 
 
 if __name__ == "__main__":

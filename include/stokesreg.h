@@ -19,7 +19,10 @@
  *
  * Conventions common to every entry point
  *   - Every array argument is a DEVICE pointer (HBM of the context's GPU), double precision,
- *     row-major: a "(k,3)" array holds k consecutive xyz triples; a "(k)" array k scalars.
+ *     row-major: a "(k,3)" array holds k consecutive xyz triples; a "(k)" array k scalars.  The
+ *     evaluation calls sr_eval and sr_eval_far also accept HOST pointers when SR_HOST is or'ed into
+ *     `layers`; they then copy through device buffers of the context and return after the results
+ *     are back in host memory.
  *   - Arrays are borrowed for the duration of the call; the library copies what it keeps.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it and the call
  *     returns without waiting, except for the set-up calls noted below.  Calls on one context must
@@ -47,11 +50,14 @@ typedef enum {
     SR_ENODEV = -3,  /* no GPU, or the requested device ordinal does not exist              */
     SR_ESTATE = -4,  /* call out of order (e.g. sr_eval before the surface/density is set)  */
     SR_EHIP = -5,    /* a HIP runtime call or kernel launch failed                          */
-    SR_ENOCONV = -6  /* an iterative solve did not reach its tolerance                      */
+    SR_ENOCONV = -6, /* an iterative solve did not reach its tolerance                      */
+    SR_ENEAR = -7    /* a target treated as far from the surface lies within the near radius
+                        of a source (reported by sr_check)                                  */
 } sr_status;
 
-/* Layer selection bits for sr_set_density / sr_eval. */
-enum { SR_SL = 1, SR_DL = 2 };
+/* Layer selection bits for sr_set_density / sr_eval.  SR_HOST (sr_eval, sr_eval_far only): the
+ * array arguments are host pointers. */
+enum { SR_SL = 1, SR_DL = 2, SR_HOST = 16 };
 
 /* Far-field precision.  SR_FP64: every sum in double.  SR_MIXED: far-field pair kernels in single
  * precision with double accumulation of 32-pair partial sums; the near regularized sums, the
@@ -95,7 +101,7 @@ sr_status sr_destroy(sr_ctx *c);
 sr_status sr_set_params(sr_ctx *c, const sr_params *p);
 
 /* Set the surface quadrature (paper section 2.2, eq. (quadrature)): n points x (n,3), outward unit
- * normals nrm (n,3) and weights w (n).  n >= 1.  The data are copied; this call synchronizes
+ * normals nrm (n,3) and weights w (n).  1 <= n <= sr_max_targets().  The data are copied; this call synchronizes
  * `stream` (it reads the points back to build the spatial index on the host).  Invalidates any
  * densities set before. */
 sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nrm, const double *w,
@@ -106,14 +112,19 @@ sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nr
  * Copied; asynchronous on `stream`. */
 sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream);
 
-/* Evaluate the extrapolated layer potentials at m targets.
- *   layers      SR_SL, SR_DL or SR_SL|SR_DL (both in one pass, sharing the pair geometry).
+/* Evaluate the extrapolated layer potentials at m targets (paper section 2, eqs. (Stokes_SL1),
+ * (Stokes_DL1), (extrap_eqn); y = x0 + b n0 as defined there).
+ *   layers      SR_SL, SR_DL or SR_SL|SR_DL (both in one pass, sharing the pair geometry); | SR_HOST
+ *               for host arrays (the call then synchronizes `stream`).
+ *   m           0 <= m <= sr_max_targets() (2^28); SR_EINVAL otherwise.
  *   y (m,3)     target points.
  *   x0 (m,3)    closest point on the surface to each target;  n0 (m,3) the outward unit normal there;
  *   b (m)       signed distance, y = x0 + b n0 (b > 0 outside, b < 0 inside, b == 0 on the surface).
- *               For a target farther than 6 max_j delta_j from the surface, x0 and n0 may be any
- *               point and unit vector and b any number of magnitude >= 6 max_j delta_j with the
- *               right sign: no smoothing acts there and the subtraction terms integrate to zero.
+ *               A target with |b| >= cutoff max_j delta_j takes the far rule: one smoothing length, no
+ *               extrapolation (every pair is beyond the cut-off there).  If such a target has a
+ *               source closer than cutoff max_j delta_j, its b (or x0) is wrong; the evaluation still
+ *               completes and the next sr_check returns SR_ENEAR.  Targets with no closest point
+ *               belong to sr_eval_far.
  *   f0 (m,3)    f(x0), needed if SR_SL is requested (else may be NULL);
  *   q0 (m,3)    q(x0), needed if SR_DL is requested (else may be NULL).
  *   u (m,3)     output single layer (if SR_SL);  v (m,3) output double layer incl. chi q(x0) (if SR_DL).
@@ -128,6 +139,25 @@ sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
 sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const double *x0, const double *n0,
                   const double *b, const double *f0, const double *q0, double *u, double *v,
                   double *u_delta, double *v_delta, void *stream);
+
+/* Evaluate the layer potentials at m targets that have no closest point (targets far from the
+ * surface, e.g. a flow field): the plain sums of eqs. (Stokes_SL), (Stokes_DL) with the original
+ * kernels (Stokeslet), (Stresslet), no subtraction and no regularization,
+ *   u = 1/(8 pi) sum_p S(y, x_p) f_p w_p,   v = 1/(8 pi) sum_p T(y, x_p) q_p n_p w_p,
+ * which is accurate only where no source lies within the near radius (paper section 3.3).  Pairs
+ * inside the near radius are left out and the target is reported: the next sr_check returns
+ * SR_ENEAR.  Direct far-field sum whatever far_method says.  layers as sr_eval (SR_HOST accepted);
+ * y (m,3); u (m,3) if SR_SL, v (m,3) if SR_DL; 0 <= m <= sr_max_targets(). */
+sr_status sr_eval_far(sr_ctx *c, int layers, int64_t m, const double *y, double *u, double *v, void *stream);
+
+/* Wait for `stream` and the context's own stream, then report the targets of the evaluations since
+ * the last sr_check that were treated as far from the surface while a source lay within the near
+ * radius: SR_ENEAR (sr_last_error names the first such target and the call that met it), SR_OK if
+ * none.  Clears the report. */
+sr_status sr_check(sr_ctx *c, void *stream);
+
+/* Largest number of targets (and of surface points) the evaluation calls accept: 2^28. */
+int64_t sr_max_targets(void);
 
 /* Per-phase timing.  While profiling is on, every sr_eval runs its phases one after the other on
  * its stream (not concurrently) and records HIP events around each: SR_PHASE_FAR (the far-field

@@ -12,16 +12,16 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstokesreg.so")
 
-SR_OK, SR_EINVAL, SR_ENOMEM, SR_ENODEV, SR_ESTATE, SR_EHIP, SR_ENOCONV = 0, -1, -2, -3, -4, -5, -6
-SR_SL, SR_DL = 1, 2
+SR_OK, SR_EINVAL, SR_ENOMEM, SR_ENODEV, SR_ESTATE, SR_EHIP, SR_ENOCONV, SR_ENEAR = 0, -1, -2, -3, -4, -5, -6, -7
+SR_SL, SR_DL, SR_HOST = 1, 2, 16
 SR_FP64, SR_MIXED = 0, 1
 SR_DIRECT, SR_TREE = 0, 1
 _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR_ESTATE", -5: "SR_EHIP",
-          -6: "SR_ENOCONV"}
+          -6: "SR_ENOCONV", -7: "SR_ENEAR"}
 
 # every symbol the header declares; the CPU test-suite checks that the library exports each one
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
-           "sr_eval", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+           "sr_eval", "sr_eval_far", "sr_check", "sr_max_targets", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
            "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
            "sr_rigid_solve_refined", "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
            "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
@@ -65,6 +65,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_set_surface.argtypes = [vp, i64, vp, vp, vp, vp]
     L.sr_set_density.argtypes = [vp, C.c_int, vp, vp]
     L.sr_eval.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.sr_eval_far.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp]
+    L.sr_check.argtypes = [vp, vp]
+    L.sr_max_targets.argtypes = []
+    L.sr_max_targets.restype = i64
     L.sr_set_profiling.argtypes = [vp, C.c_int]
     L.sr_get_profile.argtypes = [vp, d, C.POINTER(C.c_int64)]
     L.sr_tree_work.argtypes = [vp, i64, vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -117,7 +121,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_version.argtypes = []
     L.sr_version.restype = C.c_char_p
     for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
-               "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+               "sr_eval_far", "sr_check", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
                "sr_rigid_set_params",
                "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_solve_refined",
                "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity"):
@@ -201,6 +205,58 @@ def sr_eval(ctx, layers: int, y, x0, n0, b, f0=None, q0=None, u=None, v=None, u_
                                              _ptr(n0, "n0", 3), _ptr(b, "b"), _ptr(f0, "f0"), _ptr(q0, "q0"),
                                              _ptr(u, "u"), _ptr(v, "v"), _ptr(u_delta, "u_delta"),
                                              _ptr(v_delta, "v_delta"), _stream(stream)))
+
+
+def sr_eval_far(ctx, layers: int, y, u=None, v=None, stream=None) -> None:
+    """Plain sums at targets with no closest point (device tensors)."""
+    m = int(y.shape[0])
+    for name, t in (("u", u), ("v", v)):
+        if t is not None and tuple(t.shape) != (m, 3):
+            raise ValueError(f"sr_eval_far: {name} must have shape ({m}, 3)")
+    _check("sr_eval_far", load_library().sr_eval_far(ctx, int(layers), m, _ptr(y, "y", 3), _ptr(u, "u"),
+                                                     _ptr(v, "v"), _stream(stream)))
+
+
+def _hptr(a, name, shape, writable=False):
+    """Host pointer of a C-contiguous float64 numpy array of the given shape (None -> NULL)."""
+    import numpy as np
+
+    if a is None:
+        return None
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+        raise TypeError(f"{name}: expected a C-contiguous float64 numpy array")
+    if a.shape != shape:
+        raise ValueError(f"{name}: expected shape {shape}, got {a.shape}")
+    if writable and not a.flags["WRITEABLE"]:
+        raise ValueError(f"{name}: not writable")
+    return C.c_void_p(a.ctypes.data)
+
+
+def sr_eval_host(ctx, layers: int, y, x0, n0, b, f0=None, q0=None, u=None, v=None, stream=None) -> None:
+    """sr_eval with host (numpy) arrays: SR_HOST mode, synchronous."""
+    m = int(y.shape[0])
+    _check("sr_eval", load_library().sr_eval(
+        ctx, int(layers) | SR_HOST, m, _hptr(y, "y", (m, 3)), _hptr(x0, "x0", (m, 3)), _hptr(n0, "n0", (m, 3)),
+        _hptr(b, "b", (m,)), _hptr(f0, "f0", (m, 3)), _hptr(q0, "q0", (m, 3)), _hptr(u, "u", (m, 3), True),
+        _hptr(v, "v", (m, 3), True), None, None, _stream(stream)))
+
+
+def sr_eval_far_host(ctx, layers: int, y, u=None, v=None, stream=None) -> None:
+    """sr_eval_far with host (numpy) arrays: SR_HOST mode, synchronous."""
+    m = int(y.shape[0])
+    _check("sr_eval_far", load_library().sr_eval_far(ctx, int(layers) | SR_HOST, m, _hptr(y, "y", (m, 3)),
+                                                     _hptr(u, "u", (m, 3), True), _hptr(v, "v", (m, 3), True),
+                                                     _stream(stream)))
+
+
+def sr_check(ctx, stream=None) -> None:
+    """Raises SrError(SR_ENEAR) if a target treated as far from the surface had a source within the near
+    radius since the last check (waits for the stream)."""
+    _check("sr_check", load_library().sr_check(ctx, _stream(stream)))
+
+
+def sr_max_targets() -> int:
+    return int(load_library().sr_max_targets())
 
 
 def sr_set_profiling(ctx, on: bool) -> None:

@@ -103,9 +103,13 @@ struct sr_ctx {
     DevBuf<Pos4<float>> pos32;
     DevBuf<double> part;  // far-field partial sums
     DevBuf<FrontierRec> t_front;
+    DevBuf<double> stage;  // device copies of the caller's host arrays (SR_HOST)
+    NearFlag *flag = nullptr;     // target-consistency report (sr_check), device memory
+    double extent = 0.0;          // max over the points of max_d |x_d - org_d|
 
     CellGrid grid{};
     double grid_rnear = -1.0;
+    int grid_precision = -1;  // the precision the grid's margin was sized for
     double org[3] = {0.0, 0.0, 0.0};  // centre of the points' bounding box: origin of the FP32 coordinates
     bool layout_dirty = true, pack_dirty = true;
 
@@ -151,6 +155,8 @@ struct sr_ctx {
         pos32.release();
         part.release();
         t_front.release();
+        stage.release();
+        if (flag) (void)hipFree(flag);
         t_nodes.release();
         t_item_node.release();
         t_item_begin.release();
@@ -184,9 +190,11 @@ double near_radius(const sr_params &p)
     return p.cutoff * r * p.h;
 }
 
-// Uniform grid of cells of side >= the near radius (plus a relative margin of 1e-5, so that a pair
-// classified near by the single-precision test always lies in neighbouring cells), sources sorted
-// by cell with a stable counting sort.
+// Uniform grid of cells of side >= the near radius plus a margin, so that every pair the near test
+// calls near lies in neighbouring cells; sources sorted by cell with a stable counting sort.  The
+// single-precision test rounds each coordinate relative to org (error <= 2^-24 |x - org| per
+// coordinate, and as much again in the difference and the sum of squares), so the margin grows with
+// the extent E of the points: 4 * 2^-24 * (2 E + rnear) on the mixed path, plus a relative 1e-5.
 sr_status build_layout(sr_ctx *c, hipStream_t s)
 {
     const double rnear = near_radius(c->prm);
@@ -202,6 +210,7 @@ sr_status build_layout(sr_ctx *c, hipStream_t s)
             hi[d] = std::max(hi[d], c->hx[3 * i + d]);
         }
     double side = rnear * (1.0 + 1e-5);
+    if (c->prm.precision == SR_MIXED) side += 4.0 * std::ldexp(1.0, -24) * (2.0 * c->extent + rnear);
     const int64_t kMaxCells = int64_t(1) << 22;
     int g[3];
     for (;;) {
@@ -244,6 +253,7 @@ sr_status build_layout(sr_ctx *c, hipStream_t s)
     }
     c->grid.inv_side = inv_side;
     c->grid_rnear = rnear;
+    c->grid_precision = c->prm.precision;
     c->layout_dirty = false;
     c->pack_dirty = true;
     return SR_OK;
@@ -251,7 +261,7 @@ sr_status build_layout(sr_ctx *c, hipStream_t s)
 
 sr_status ensure_packed(sr_ctx *c, hipStream_t s)
 {
-    if (c->layout_dirty || c->grid_rnear != near_radius(c->prm)) {
+    if (c->layout_dirty || c->grid_rnear != near_radius(c->prm) || c->grid_precision != c->prm.precision) {
         sr_status st = build_layout(c, s);
         if (st != SR_OK) return st;
     }
@@ -411,6 +421,14 @@ sr_status sr_create(sr_ctx **out, int device)
             delete c;
             return fail(SR_EHIP, "sr_create: stream or event creation failed: %s", hipGetErrorString(e));
         }
+        // the target-consistency report, cleared
+        e = hipMalloc((void **)&c->flag, sizeof(NearFlag));
+        if (e == hipSuccess) e = launch_flag_clear(c->flag, c->side);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->side);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(e == hipErrorOutOfMemory ? SR_ENOMEM : SR_EHIP, "sr_create: %s", hipGetErrorString(e));
+        }
     }
     *out = c;
     return SR_OK;
@@ -462,7 +480,8 @@ sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nr
 {
     g_err.clear();
     if (!c) return fail(SR_EINVAL, "sr_set_surface: ctx is NULL");
-    if (n < 1 || n > (int64_t(1) << 30)) return fail(SR_EINVAL, "sr_set_surface: n = %lld out of range", (long long)n);
+    if (n < 1 || n > kMaxTargets)
+        return fail(SR_EINVAL, "sr_set_surface: n = %lld out of range (1..%lld)", (long long)n, (long long)kMaxTargets);
     if (!x || !nrm || !w) return fail(SR_EINVAL, "sr_set_surface: NULL array");
     DeviceGuard g(c->device);
     if (!g.ok) return fail(SR_ENODEV, "sr_set_surface: cannot select device %d", c->device);
@@ -486,6 +505,7 @@ sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nr
     SR_HIP(hipMemcpyAsync(c->nrm.p, nrm, 3 * n * sizeof(double), hipMemcpyDeviceToDevice, s));
     SR_HIP(hipMemcpyAsync(c->w.p, w, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     c->n = n;
+    c->extent = 0.0;
     for (int d = 0; d < 3; ++d) {
         double lo = hx[d], hi = hx[d];
         for (int64_t i = 1; i < n; ++i) {
@@ -493,6 +513,7 @@ sr_status sr_set_surface(sr_ctx *c, int64_t n, const double *x, const double *nr
             hi = std::max(hi, hx[3 * i + d]);
         }
         c->org[d] = 0.5 * (lo + hi);
+        c->extent = std::max(c->extent, 0.5 * (hi - lo));
     }
     c->hx.swap(hx);
     c->have_surface = true;
@@ -524,29 +545,31 @@ sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
     return SR_OK;
 }
 
-sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const double *x0, const double *n0,
-                  const double *b, const double *f0, const double *q0, double *u, double *v, double *u_delta,
-                  double *v_delta, void *stream)
-{
-    g_err.clear();
-    if (!c) return fail(SR_EINVAL, "sr_eval: ctx is NULL");
-    if (layers != SR_SL && layers != SR_DL && layers != (SR_SL | SR_DL))
-        return fail(SR_EINVAL, "sr_eval: layers must be SR_SL, SR_DL or both");
-    if (m < 0 || m > (int64_t(1) << 30)) return fail(SR_EINVAL, "sr_eval: m = %lld out of range", (long long)m);
-    if (!c->have_params) return fail(SR_ESTATE, "sr_eval: parameters not set");
-    if (!c->have_surface) return fail(SR_ESTATE, "sr_eval: surface not set");
-    if ((layers & SR_SL) && !c->have_sl) return fail(SR_ESTATE, "sr_eval: single-layer density not set");
-    if ((layers & SR_DL) && !c->have_dl) return fail(SR_ESTATE, "sr_eval: double-layer density not set");
-    if (m == 0) return SR_OK;
-    if (!y || !x0 || !n0 || !b) return fail(SR_EINVAL, "sr_eval: NULL target array");
-    if ((layers & SR_SL) && (!f0 || !u)) return fail(SR_EINVAL, "sr_eval: SR_SL needs f0 and u");
-    if ((layers & SR_DL) && (!q0 || !v)) return fail(SR_EINVAL, "sr_eval: SR_DL needs q0 and v");
-    DeviceGuard g(c->device);
-    if (!g.ok) return fail(SR_ENODEV, "sr_eval: cannot select device %d", c->device);
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
 
-    sr_status st = ensure_packed(c, s);
-    if (st != SR_OK) return st;
+// The evaluation on device arrays (sr::eval_on_device in sr_internal.h).
+sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, const double *y, const double *x0,
+                             const double *n0, const double *b, const double *f0, const double *q0, double *u,
+                             double *v, double *u_delta, double *v_delta, hipStream_t s, double *ext_part)
+{
+    sr_status st;
+    const bool noalloc = ext_part != nullptr;
+    if (noalloc) {
+        if (c->prm.far_method == SR_TREE) return fail(SR_EINVAL, "%s: the treecode far field is not supported", fn);
+        if (c->layout_dirty || c->grid_rnear != near_radius(c->prm) || c->grid_precision != c->prm.precision ||
+            c->rec64.cap < (size_t)c->n)
+            return fail(SR_ESTATE, "%s: the context's cell list and records are not built for the current surface "
+                                   "and parameters (one sr_eval call builds them)", fn);
+        if (c->pack_dirty) {
+            // densities changed: repack into the existing records (no allocation)
+            SR_HIP(launch_pack(c->x.p, c->nrm.p, c->w.p, c->have_sl ? c->f.p : nullptr,
+                               c->have_dl ? c->q.p : nullptr, c->perm.p, c->n, c->org, c->rec64.p, c->rec32.p,
+                               c->pos64.p, c->pos32.p, s));
+            c->pack_dirty = false;
+        }
+    } else if ((st = ensure_packed(c, s)) != SR_OK) {
+        return st;
+    }
 
     EvalArgs a{};
     a.layers = layers;
@@ -574,6 +597,10 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
     }
     dp.cutoff = c->prm.cutoff;
     dp.rnear = c->grid_rnear;
+    // a far-rule target (|b| >= cutoff * max delta) with a source closer than cutoff * max delta, less
+    // the near test's rounding (relative 1e-4 on the mixed path's single-precision squared distance,
+    // 1e-9 in double precision), is reported
+    dp.rflag = c->prm.cutoff * dp.rho[2] * c->prm.h * (c->prm.precision == SR_MIXED ? 1.0 - 1e-4 : 1.0 - 1e-9);
     dp.precision = c->prm.precision;
     dp.pow234 = (2.0 * dp.rho[1] == 3.0 * dp.rho[0] && dp.rho[2] == 2.0 * dp.rho[0]) ? 1 : 0;
     dp.sharp = c->prm.surface_sharp ? 1 : 0;
@@ -599,16 +626,24 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
         D.sort_tmp_bytes = c->t_sort_tmp.cap;
         nparts = c->tdev.nfront;
     }
-    SR_HIP(c->part.reserve((size_t)nparts * 6 * (size_t)m));
+    double *part;
+    if (noalloc) {
+        part = ext_part;
+    } else {
+        SR_HIP(c->part.reserve((size_t)nparts * 6 * (size_t)m));
+        part = c->part.p;
+    }
     // Without per-delta outputs and without profiling, the near-field kernel (near sums,
     // extrapolation, jump term) runs on the side stream concurrently with the far field, and
     // launch_far_add then adds the far sum on the caller's stream.  Both kernels are bound by vector
     // ALU issue but stall differently, and the near kernel's short one-target wavefronts fill the
     // issue cycles and the wave slots the far kernel leaves (8.5% less time at the 42k-source
-    // ellipsoid).  With profiling on, the phases run one after the other so that each has its own time.
-    const bool concurrent = !c->profiling && !u_delta && !v_delta;
+    // ellipsoid).  With profiling on, the phases run one after the other so that each has its own
+    // time (the no-alloc variant records no events: it runs the phases concurrently).
+    const bool profile = c->profiling && !noalloc;
+    const bool concurrent = !profile && !u_delta && !v_delta;
     if (concurrent) SR_HIP(hipEventRecord(c->ev_fork, s));
-    if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
+    if (profile && (st = record_event(c, s)) != SR_OK) return st;
     if (tree) {
         // Morton order over the sources' cell grid box, 1024 steps per axis
         const TreeNode &root = c->tree.nodes[0];
@@ -620,10 +655,10 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
         }
         SR_HIP(launch_target_order(y, (int)m, lo, 1024.0 / ext, c->tdev, s));
         SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear, dp.rsharp, dp.sharp,
-                               c->part.p, s));
+                               part, s));
     } else {
         SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, dp.rsharp,
-                                 dp.sharp, c->part.p, s));
+                                 dp.sharp, part, s));
     }
     if (concurrent) {
         // the side stream starts after everything the caller enqueued before this call (fork) and
@@ -631,21 +666,186 @@ sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const doubl
         hipError_t e0 = hipStreamWaitEvent(c->side, c->ev_fork, 0);
         hipError_t e1 = e0 == hipSuccess
                             ? launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p,
-                                                   c->cell_start.p, c->grid, a, dp, nullptr, 0, c->side)
+                                                   c->cell_start.p, c->grid, a, dp, nullptr, 0, c->flag, c->side)
                             : e0;
         hipError_t e2 = hipEventRecord(c->ev_join, c->side);
         hipError_t e3 = hipStreamWaitEvent(s, c->ev_join, 0);
         for (hipError_t e : {e0, e1, e2, e3})
-            if (e != hipSuccess) return fail(SR_EHIP, "sr_eval: %s", hipGetErrorString(e));
-        SR_HIP(launch_far_add(layers, c->part.p, nparts, a, s));
+            if (e != hipSuccess) return fail(SR_EHIP, "%s: %s", fn, hipGetErrorString(e));
+        SR_HIP(launch_far_add(layers, part, nparts, a, false, s));
         return SR_OK;
     }
-    if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
+    if (profile && (st = record_event(c, s)) != SR_OK) return st;
     SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p, c->cell_start.p,
-                                c->grid, a, dp, c->part.p, nparts, s));
-    if (c->profiling && (st = record_event(c, s)) != SR_OK) return st;
+                                c->grid, a, dp, part, nparts, c->flag, s));
+    if (profile && (st = record_event(c, s)) != SR_OK) return st;
     return SR_OK;
 }
+
+// Validation shared by the evaluation entry points: argument checks first (so that they can be tested
+// without a context), then the context's state.
+sr_status sr::eval_check(const char *fn, sr_ctx *c, int layers, int64_t m, int64_t max_m)
+{
+    if (layers != SR_SL && layers != SR_DL && layers != (SR_SL | SR_DL))
+        return fail(SR_EINVAL, "%s: layers must be SR_SL, SR_DL or both (with SR_HOST where accepted)", fn);
+    if (m < 0 || m > max_m)
+        return fail(SR_EINVAL, "%s: m = %lld out of range (0..%lld)", fn, (long long)m, (long long)max_m);
+    if (!c) return fail(SR_EINVAL, "%s: ctx is NULL", fn);
+    if (!c->have_params) return fail(SR_ESTATE, "%s: parameters not set", fn);
+    if (!c->have_surface) return fail(SR_ESTATE, "%s: surface not set", fn);
+    if ((layers & SR_SL) && !c->have_sl) return fail(SR_ESTATE, "%s: single-layer density not set", fn);
+    if ((layers & SR_DL) && !c->have_dl) return fail(SR_ESTATE, "%s: double-layer density not set", fn);
+    return SR_OK;
+}
+
+sr_status sr::set_error(sr_status st, const char *msg)
+{
+    return fail(st, "%s", msg);
+}
+
+int sr::ctx_device(const sr_ctx *c) { return c->device; }
+
+extern "C" {
+
+// Host arrays of an SR_HOST call: device copies in the context's staging buffer, in the order given;
+// outputs are copied back by stage_out.
+struct Staged {
+    const double *src;
+    double **dst;
+    size_t count;
+    bool in;
+};
+
+static sr_status stage_in(const char *fn, sr_ctx *c, std::vector<Staged> &arr, hipStream_t s)
+{
+    size_t tot = 0;
+    for (const Staged &a : arr)
+        if (a.src) tot += a.count;
+    SR_HIP(c->stage.reserve(tot));
+    size_t off = 0;
+    for (Staged &a : arr) {
+        if (!a.src) {
+            *a.dst = nullptr;
+            continue;
+        }
+        *a.dst = c->stage.p + off;
+        if (a.in) SR_HIP(hipMemcpyAsync(*a.dst, a.src, a.count * sizeof(double), hipMemcpyHostToDevice, s));
+        off += a.count;
+    }
+    (void)fn;
+    return SR_OK;
+}
+
+static sr_status stage_out(sr_ctx *c, const std::vector<Staged> &arr, hipStream_t s)
+{
+    (void)c;
+    for (const Staged &a : arr)
+        if (a.src && !a.in)
+            SR_HIP(hipMemcpyAsync((void *)a.src, *a.dst, a.count * sizeof(double), hipMemcpyDeviceToHost, s));
+    SR_HIP(hipStreamSynchronize(s));
+    return SR_OK;
+}
+
+sr_status sr_eval(sr_ctx *c, int layers, int64_t m, const double *y, const double *x0, const double *n0,
+                  const double *b, const double *f0, const double *q0, double *u, double *v, double *u_delta,
+                  double *v_delta, void *stream)
+{
+    g_err.clear();
+    const bool host = (layers & SR_HOST) != 0;
+    layers &= ~SR_HOST;
+    sr_status st = eval_check("sr_eval", c, layers, m, kMaxTargets);
+    if (st != SR_OK) return st;
+    if (m == 0) return SR_OK;
+    if (!y || !x0 || !n0 || !b) return fail(SR_EINVAL, "sr_eval: NULL target array");
+    if ((layers & SR_SL) && (!f0 || !u)) return fail(SR_EINVAL, "sr_eval: SR_SL needs f0 and u");
+    if ((layers & SR_DL) && (!q0 || !v)) return fail(SR_EINVAL, "sr_eval: SR_DL needs q0 and v");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(SR_ENODEV, "sr_eval: cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (!host) return eval_on_device("sr_eval", c, layers, m, y, x0, n0, b, f0, q0, u, v, u_delta, v_delta, s, nullptr);
+
+    const size_t m3 = 3 * (size_t)m;
+    const double *dy, *dx0, *dn0, *db, *df0, *dq0;
+    double *du, *dv, *dud, *dvd;
+    std::vector<Staged> arr = {
+        {y, (double **)&dy, m3, true},
+        {x0, (double **)&dx0, m3, true},
+        {n0, (double **)&dn0, m3, true},
+        {b, (double **)&db, (size_t)m, true},
+        {(layers & SR_SL) ? f0 : nullptr, (double **)&df0, m3, true},
+        {(layers & SR_DL) ? q0 : nullptr, (double **)&dq0, m3, true},
+        {(layers & SR_SL) ? u : nullptr, &du, m3, false},
+        {(layers & SR_DL) ? v : nullptr, &dv, m3, false},
+        {(layers & SR_SL) ? u_delta : nullptr, &dud, 3 * m3, false},
+        {(layers & SR_DL) ? v_delta : nullptr, &dvd, 3 * m3, false},
+    };
+    if ((st = stage_in("sr_eval", c, arr, s)) != SR_OK) return st;
+    if ((st = eval_on_device("sr_eval", c, layers, m, dy, dx0, dn0, db, df0, dq0, du, dv, dud, dvd, s, nullptr)) !=
+        SR_OK)
+        return st;
+    return stage_out(c, arr, s);
+}
+
+sr_status sr_eval_far(sr_ctx *c, int layers, int64_t m, const double *y, double *u, double *v, void *stream)
+{
+    g_err.clear();
+    const bool host = (layers & SR_HOST) != 0;
+    layers &= ~SR_HOST;
+    sr_status st = eval_check("sr_eval_far", c, layers, m, kMaxTargets);
+    if (st != SR_OK) return st;
+    if (m == 0) return SR_OK;
+    if (!y) return fail(SR_EINVAL, "sr_eval_far: y is NULL");
+    if ((layers & SR_SL) && !u) return fail(SR_EINVAL, "sr_eval_far: SR_SL needs u");
+    if ((layers & SR_DL) && !v) return fail(SR_EINVAL, "sr_eval_far: SR_DL needs v");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(SR_ENODEV, "sr_eval_far: cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_packed(c, s)) != SR_OK) return st;
+    const size_t m3 = 3 * (size_t)m;
+    const double *dy = y;
+    double *du = u, *dv = v;
+    std::vector<Staged> arr = {
+        {y, (double **)&dy, m3, true},
+        {(layers & SR_SL) ? u : nullptr, &du, m3, false},
+        {(layers & SR_DL) ? v : nullptr, &dv, m3, false},
+    };
+    if (host && (st = stage_in("sr_eval_far", c, arr, s)) != SR_OK) return st;
+    EvalArgs a{};
+    a.layers = layers;
+    a.m = m;
+    a.y = dy;
+    a.u = du;
+    a.v = dv;
+    for (int d = 0; d < 3; ++d) a.org[d] = c->prm.precision == SR_MIXED ? c->org[d] : 0.0;
+    SR_HIP(c->part.reserve((size_t)kFarSplits * 6 * (size_t)m));
+    SR_HIP(launch_far_plain(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, c->grid_rnear, c->flag,
+                            c->part.p, s));
+    SR_HIP(launch_far_add(layers, c->part.p, kFarSplits, a, true, s));
+    return host ? stage_out(c, arr, s) : SR_OK;
+}
+
+sr_status sr_check(sr_ctx *c, void *stream)
+{
+    g_err.clear();
+    if (!c) return fail(SR_EINVAL, "sr_check: ctx is NULL");
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(SR_ENODEV, "sr_check: cannot select device %d", c->device);
+    hipStream_t s = (hipStream_t)stream;
+    NearFlag hf{};
+    SR_HIP(hipStreamSynchronize(s));
+    SR_HIP(hipStreamSynchronize(c->side));
+    SR_HIP(hipMemcpy(&hf, c->flag, sizeof hf, hipMemcpyDeviceToHost));
+    if (hf.bits == 0) return SR_OK;
+    SR_HIP(launch_flag_clear(c->flag, s));
+    SR_HIP(hipStreamSynchronize(s));
+    if (hf.bits & kFlagFarTarget)
+        return fail(SR_ENEAR, "sr_check: target %llu of sr_eval_far lies within the near radius of a source: it needs "
+                              "its closest point and sr_eval", hf.first);
+    return fail(SR_ENEAR, "sr_check: target %llu of sr_eval has |b| >= cutoff * max delta (far rule, no "
+                          "extrapolation) but a source closer than that: b or x0 is wrong", hf.first);
+}
+
+int64_t sr_max_targets(void) { return kMaxTargets; }
 
 sr_status sr_tree_work(sr_ctx *c, int64_t m, const double *y, int64_t *proxy_pairs, int64_t *leaf_pairs,
                        int64_t *cluster_points)

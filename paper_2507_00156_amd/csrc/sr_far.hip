@@ -16,6 +16,11 @@
 //   - output: per-split partial sums part[split][channel][target], channel 0..2 = single-layer
 //     sum of S g, channel 3..5 = sum of d (d.a)(d.m) / r^5 (the -6 and 1/(8 pi) are applied
 //     when the near-field kernel combines the parts).
+// Targets with no closest point (PLAIN instance, sr_eval_far): g = f w and a = q, the plain sums of
+// eqs. (Stokes_SL), (Stokes_DL) with no subtraction; a target that has a pair inside the near radius
+// needs the near-field treatment (and x0) and is reported in the context's NearFlag.  Such targets
+// may lie far from the single-precision origin, where rounding y - org to FP32 would move them by
+// 2^-24 |y - org|: the instance keeps the rounding remainder y_lo and forms d = (y_hi - x) + y_lo.
 #include "sr_internal.h"
 
 namespace sr {
@@ -49,22 +54,24 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // PT: per-target near radius (the modified smoothing is on); otherwise rc2 for every target, kept in a
-// scalar register (a per-lane radius costs 4% of the mixed-precision kernel)
-template <typename T, bool SL, bool DL, int TPL, bool PT>
+// scalar register (a per-lane radius costs 4% of the mixed-precision kernel).  PLAIN: no subtraction,
+// near pairs reported in *flag.
+template <typename T, bool SL, bool DL, int TPL, bool PT, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__restrict__ src, int n, int chunk,
                                                             const double *__restrict__ y,
                                                             const double *__restrict__ n0,
                                                             const double *__restrict__ f0,
                                                             const double *__restrict__ q0,
                                                             const double *__restrict__ bt, int m, T rc2, T rc2s,
-                                                            Org3 org, double *__restrict__ part)
+                                                            Org3 org, NearFlag *__restrict__ flag,
+                                                            double *__restrict__ part)
 {
     const int split = blockIdx.x % kFarSplits;
     const int tile = blockIdx.x / kFarSplits;
     const int p0 = split * chunk;
     const int p1 = min(n, p0 + chunk);
 
-    T ty[TPL][3], tc[TPL], tq[TPL][3], tr2[TPL];
+    T ty[TPL][3], tc[TPL], tq[TPL][3], tr2[TPL], tlo[TPL][3];
     int tix[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -72,14 +79,22 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
         tix[k] = t;
         const int tt = t < m ? t : m - 1;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) ty[k][i] = (T)(y[3 * tt + i] - org[i]);
+        for (int i = 0; i < 3; ++i) {
+            const double yr = y[3 * tt + i] - org[i];
+            ty[k][i] = (T)yr;
+            tlo[k][i] = (T)(yr - (double)ty[k][i]);  // zero in double precision
+        }
         tc[k] = 0;
-        if (SL) tc[k] = (T)(f0[3 * tt] * n0[3 * tt] + f0[3 * tt + 1] * n0[3 * tt + 1] + f0[3 * tt + 2] * n0[3 * tt + 2]);
+        if (SL && !PLAIN)
+            tc[k] = (T)(f0[3 * tt] * n0[3 * tt] + f0[3 * tt + 1] * n0[3 * tt + 1] + f0[3 * tt + 2] * n0[3 * tt + 2]);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) tq[k][i] = DL ? (T)q0[3 * tt + i] : (T)0;
+        for (int i = 0; i < 3; ++i) tq[k][i] = (DL && !PLAIN) ? (T)q0[3 * tt + i] : (T)0;
         // a target on the surface under the modified smoothing has the smaller near radius
         tr2[k] = (PT && bt[tt] == 0.0) ? rc2s : rc2;
     }
+    bool has_near[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) has_near[k] = false;
 
     double acc[TPL][6];
 #pragma unroll
@@ -99,9 +114,18 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
             const SrcRec<T> s = src[p];
 #pragma unroll
             for (int k = 0; k < TPL; ++k) {
-                const T dx = ty[k][0] - s.x, dy = ty[k][1] - s.y, dz = ty[k][2] - s.z;
-                const T r2 = pair_r2(ty[k][0], ty[k][1], ty[k][2], s.x, s.y, s.z);
+                T dx = ty[k][0] - s.x, dy = ty[k][1] - s.y, dz = ty[k][2] - s.z;
+                T r2;
+                if (PLAIN && sizeof(T) == 4) {
+                    dx += tlo[k][0];
+                    dy += tlo[k][1];
+                    dz += tlo[k][2];
+                    r2 = fma_t(dz, dz, fma_t(dy, dy, dx * dx));
+                } else {
+                    r2 = pair_r2(ty[k][0], ty[k][1], ty[k][2], s.x, s.y, s.z);
+                }
                 const T ir = far_ir(r2, tr2[k]);
+                if (PLAIN) has_near[k] = has_near[k] || !(r2 > tr2[k]);
                 const T ir2 = ir * ir;
                 const T ir3 = ir2 * ir;
                 if (SL) {
@@ -131,6 +155,15 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
             for (int c = 0; c < 6; ++c) acc[k][c] += (double)a[k][c];
     }
 
+    if (PLAIN) {
+#pragma unroll
+        for (int k = 0; k < TPL; ++k)
+            if (tix[k] < m && has_near[k]) {
+                atomicOr(&flag->bits, kFlagFarTarget);
+                atomicMin(&flag->first, (unsigned long long)tix[k]);
+            }
+    }
+
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
         if (tix[k] < m) {
@@ -145,31 +178,35 @@ __global__ __launch_bounds__(kBlock) void far_direct_kernel(const SrcRec<T> *__r
     }
 }
 
-template <typename T, bool SL, bool DL>
-hipError_t launch_t(const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, T rc2s, int sharp, double *part,
-                    hipStream_t s)
+template <typename T, bool SL, bool DL, bool PLAIN>
+hipError_t launch_t(const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, T rc2s, int sharp, NearFlag *flag,
+                    double *part, hipStream_t s)
 {
     constexpr int TPL = 2;
     const int m = (int)a.m;
     const int tiles = (m + kBlock * TPL - 1) / (kBlock * TPL);
     const int chunk = (int)((n + kFarSplits - 1) / kFarSplits);
     dim3 grid(tiles * kFarSplits), block(kBlock);
-    if (sharp)
-        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, true>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0,
-                           a.f0, a.q0, a.b, m, rc2, rc2s, Org3{a.org[0], a.org[1], a.org[2]}, part);
+    const Org3 org{a.org[0], a.org[1], a.org[2]};
+    if (PLAIN)
+        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, false, true>), grid, block, 0, s, rec, (int)n, chunk,
+                           a.y, a.n0, a.f0, a.q0, a.b, m, rc2, rc2s, org, flag, part);
+    else if (sharp)
+        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, true, false>), grid, block, 0, s, rec, (int)n, chunk,
+                           a.y, a.n0, a.f0, a.q0, a.b, m, rc2, rc2s, org, flag, part);
     else
-        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, false>), grid, block, 0, s, rec, (int)n, chunk, a.y, a.n0,
-                           a.f0, a.q0, a.b, m, rc2, rc2s, Org3{a.org[0], a.org[1], a.org[2]}, part);
+        hipLaunchKernelGGL((far_direct_kernel<T, SL, DL, TPL, false, false>), grid, block, 0, s, rec, (int)n, chunk,
+                           a.y, a.n0, a.f0, a.q0, a.b, m, rc2, rc2s, org, flag, part);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool PLAIN>
 hipError_t dispatch(int layers, const SrcRec<T> *rec, int64_t n, const EvalArgs &a, T rc2, T rc2s, int sharp,
-                    double *part, hipStream_t s)
+                    NearFlag *flag, double *part, hipStream_t s)
 {
-    if (layers == (SR_SL | SR_DL)) return launch_t<T, true, true>(rec, n, a, rc2, rc2s, sharp, part, s);
-    if (layers == SR_SL) return launch_t<T, true, false>(rec, n, a, rc2, rc2s, sharp, part, s);
-    return launch_t<T, false, true>(rec, n, a, rc2, rc2s, sharp, part, s);
+    if (layers == (SR_SL | SR_DL)) return launch_t<T, true, true, PLAIN>(rec, n, a, rc2, rc2s, sharp, flag, part, s);
+    if (layers == SR_SL) return launch_t<T, true, false, PLAIN>(rec, n, a, rc2, rc2s, sharp, flag, part, s);
+    return launch_t<T, false, true, PLAIN>(rec, n, a, rc2, rc2s, sharp, flag, part, s);
 }
 
 }  // namespace
@@ -180,8 +217,17 @@ hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *re
 {
     const double rc2 = rnear * rnear, rc2s = rsharp * rsharp;
     if (precision == SR_MIXED)
-        return dispatch<float>(layers, rec32, n, a, (float)rc2, (float)rc2s, sharp, part, s);
-    return dispatch<double>(layers, rec64, n, a, rc2, rc2s, sharp, part, s);
+        return dispatch<float, false>(layers, rec32, n, a, (float)rc2, (float)rc2s, sharp, nullptr, part, s);
+    return dispatch<double, false>(layers, rec64, n, a, rc2, rc2s, sharp, nullptr, part, s);
+}
+
+hipError_t launch_far_plain(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
+                            int64_t n, const EvalArgs &a, double rnear, NearFlag *flag, double *part, hipStream_t s)
+{
+    const double rc2 = rnear * rnear;
+    if (precision == SR_MIXED)
+        return dispatch<float, true>(layers, rec32, n, a, (float)rc2, (float)rc2, 0, flag, part, s);
+    return dispatch<double, true>(layers, rec64, n, a, rc2, rc2, 0, flag, part, s);
 }
 
 }  // namespace sr

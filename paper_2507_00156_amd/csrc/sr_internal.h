@@ -66,6 +66,21 @@ struct CellGrid {
     int g[3];
 };
 
+// Consistency report of a context's targets, written by the kernels and read by sr_check: bits
+// kFlagFarTarget (a target of sr_eval_far with a source inside the near radius) and kFlagFarRule (a
+// target of sr_eval whose |b| selects the far-field rule w = (1, 0, 0) with a source closer than
+// cutoff * max_j delta_j); `first` is the smallest offending target index.
+constexpr unsigned kFlagFarTarget = 1u, kFlagFarRule = 2u;
+struct NearFlag {
+    unsigned int bits;
+    unsigned int pad;
+    unsigned long long first;
+};
+
+// Largest number of targets of one evaluation: 3 * m stays below 2^31, so the kernels' 32-bit
+// target indices (3 t + component) cannot overflow.
+constexpr int64_t kMaxTargets = int64_t(1) << 28;
+
 struct EvalArgs {
     int layers;          // SR_SL | SR_DL bits
     int64_t m;
@@ -86,6 +101,8 @@ struct DevParams {
     int ord[3];
     double cutoff;       // in t = r / delta
     double rnear;        // cutoff * max_j delta_j (and the modified-smoothing delta if larger)
+    double rflag;        // a target with |b| >= cutoff * max_j delta_j and a source closer than this is
+                         // reported (kFlagFarRule): cutoff * max_j delta_j less a rounding margin
     int precision;
     int pow234;          // the sorted deltas are in the ratio 2 : 3 : 4 (exp(-t_j^2) by powers of one exp)
     int sharp;           // targets on the surface (b == 0) use the modified smoothing at one delta
@@ -102,12 +119,36 @@ hipError_t launch_pack(const double *x, const double *nrm, const double *w, cons
 hipError_t launch_far_direct(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
                              int64_t n, const EvalArgs &a, double rnear, double rsharp, int sharp, double *part,
                              hipStream_t s);
+// Plain sums at targets with no closest point (sr_eval_far): the original kernels applied to f w and
+// q n w with no subtraction, over every source farther than rnear; a target with a source inside rnear
+// is reported in *flag (kFlagFarTarget).  Writes the same partial sums as launch_far_direct.
+hipError_t launch_far_plain(int precision, int layers, const SrcRec<double> *rec64, const SrcRec<float> *rec32,
+                            int64_t n, const EvalArgs &a, double rnear, NearFlag *flag, double *part, hipStream_t s);
 
 hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
                                 const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,
                                 const CellGrid &grid, const EvalArgs &a, const DevParams &p, const double *part,
-                                int nparts, hipStream_t s);
-// u += far / (8 pi), v += -6 far / (8 pi) for outputs written by launch_near_finalize with nparts = 0
-hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, hipStream_t s);
+                                int nparts, NearFlag *flag, hipStream_t s);
+// u += far / (8 pi), v += -6 far / (8 pi) for outputs written by launch_near_finalize with nparts = 0;
+// with store, u = far / (8 pi), v = -6 far / (8 pi) (the plain sums of sr_eval_far)
+hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, bool store, hipStream_t s);
+// *flag = no report (bits 0, first = all ones)
+hipError_t launch_flag_clear(NearFlag *flag, hipStream_t s);
+
+// ---- the evaluation shared by the C entry points (sr_api.hip) ----
+// Checks layers (SR_SL, SR_DL or both), 0 <= m <= max_m, then the context's state; sets the thread's
+// error message.
+sr_status eval_check(const char *fn, sr_ctx *c, int layers, int64_t m, int64_t max_m);
+// The evaluation of sr_eval on device arrays.  ext_part == nullptr: the far-field partial sums go to a
+// context-owned buffer (grown as needed).  Otherwise they go to ext_part (room for kFarSplits * 6 * m
+// doubles) and nothing is allocated: SR_ESTATE if the context's cell list or records would have to be
+// built, SR_EINVAL for the treecode far field; profiling is then ignored.
+sr_status eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, const double *y, const double *x0,
+                         const double *n0, const double *b, const double *f0, const double *q0, double *u, double *v,
+                         double *u_delta, double *v_delta, hipStream_t s, double *ext_part);
+// Sets the thread's error message (sr_last_error) and returns st.
+sr_status set_error(sr_status st, const char *msg);
+// Device ordinal of a context.
+int ctx_device(const sr_ctx *c);
 
 }  // namespace sr

@@ -33,6 +33,9 @@
 // measured on MI355X, the queue bookkeeping cost more than the smoothing it saved (per-class queues:
 // 27% fewer FP64 FMAs, 19% more VALU instructions in all).
 // Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
+// A target whose |b| selects w = (1, 0, 0) lies, by its own b, at least cutoff * max delta from the
+// surface; if a source is closer than that (less a rounding margin) the caller's b is wrong and the
+// near regularization it skipped was needed: the scan reports it in the context's NearFlag.
 #include <math.h>
 
 #include <type_traits>
@@ -610,7 +613,7 @@ __device__ __forceinline__ void near_pair_sharp_full(const SrcRec<double> *__res
     }
 }
 
-// Extrapolation weights of eq. (2.10) for a target at signed distance b (the same for the single and
+// Extrapolation weights of eq. (extrap_eqn) for a target at signed distance b (the same for the single and
 // double layer and every component); far from the surface the smallest delta alone (w = 1, 0, 0).
 __device__ __forceinline__ void extrap_weights(double b, const DevParams &p, double w[3])
 {
@@ -663,7 +666,8 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
                                                                const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
                                                                EvalArgs a, DevParams p, TC rc2, TC rc2s,
-                                                               const double *__restrict__ part, int nparts)
+                                                               const double *__restrict__ part, int nparts,
+                                                               NearFlag *__restrict__ flag)
 {
     // single-precision candidate test = the mixed-precision path: the degree-11 erfcx table
     constexpr bool kLo = std::is_same<TC, float>::value;
@@ -694,6 +698,11 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
     T.c = SL ? a.f0[3 * t] * T.n[0] + a.f0[3 * t + 1] * T.n[1] + a.f0[3 * t + 2] * T.n[2] : 0.0;
     if (COMB) extrap_weights(T.b, p, T.w);
     const TC tyx = (TC)(T.y[0] - a.org[0]), tyy = (TC)(T.y[1] - a.org[1]), tyz = (TC)(T.y[2] - a.org[2]);
+    // the far rule of the extrapolation (w = (1, 0, 0)) asserts that no source is within
+    // cutoff * max delta: checked against the candidates (wavefront-uniform)
+    const bool farrule = !SHARP && fabs(T.b) >= p.cutoff * p.rho[2] * p.h;
+    const TC rflag2 = (TC)(p.rflag * p.rflag);
+    bool bad = false;
 
     int ci[3];
 #pragma unroll
@@ -730,7 +739,9 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
 #pragma unroll
                 for (int u = 0; u < kDepth; ++u) {
                     const int k = base + u * kWave + lane;
-                    const bool nr = k < s1 && pair_r2(tyx, tyy, tyz, q[u].x, q[u].y, q[u].z) <= (SHARP ? rc2s : rc2);
+                    const TC r2c = pair_r2(tyx, tyy, tyz, q[u].x, q[u].y, q[u].z);
+                    const bool nr = k < s1 && r2c <= (SHARP ? rc2s : rc2);
+                    if (farrule) bad = bad || (nr && r2c < rflag2);
                     const uint64_t m = __ballot(nr);
                     if (nr) {
                         const int off = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -752,6 +763,10 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
     }
     wave_lds_sync();
     if (lane < cnt) eval_pair<SL, DL, SHARP, P234, COMB, kLo>(rec64, queue[(head + lane) & (kRing - 1)], T, p, A);
+    if (farrule && __ballot(bad) && lane == 0) {
+        atomicOr(&flag->bits, kFlagFarRule);
+        atomicMin(&flag->first, (unsigned long long)t);
+    }
 
     constexpr int NJ = COMB ? 1 : 3;
 #pragma unroll
@@ -821,7 +836,8 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
 
 template <typename TC, bool SL, bool DL>
 hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int *cell_start, const CellGrid &g,
-                    const EvalArgs &a, const DevParams &p, TC rc2, const double *part, int nparts, hipStream_t s)
+                    const EvalArgs &a, const DevParams &p, TC rc2, const double *part, int nparts, NearFlag *flag,
+                    hipStream_t s)
 {
     const int per_block = kBlock / kWave;
     const int64_t blocks = (a.m + per_block - 1) / per_block;
@@ -830,32 +846,33 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
     const dim3 grid((unsigned)blocks), block(kBlock);
     if (p.pow234 && comb)
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, true>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, rc2s, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     else if (p.pow234)
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, false>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, rc2s, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     else if (comb)
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, true>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, rc2s, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     else
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, false>), grid, block, 0, s, rec64, pos,
-                           cell_start, g, a, p, rc2, rc2s, part, nparts);
+                           cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.sharp) return e;
     hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true, false, false>), grid, block, 0, s, rec64, pos,
-                       cell_start, g, a, p, rc2, rc2s, part, nparts);
+                       cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     return hipGetLastError();
 }
 
 template <typename TC>
 hipError_t dispatch(int layers, const SrcRec<double> *rec64, const Pos4<TC> *pos, const int *cell_start,
                     const CellGrid &g, const EvalArgs &a, const DevParams &p, TC rc2, const double *part,
-                    int nparts, hipStream_t s)
+                    int nparts, NearFlag *flag, hipStream_t s)
 {
     if (layers == (SR_SL | SR_DL))
-        return launch_t<TC, true, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
-    if (layers == SR_SL) return launch_t<TC, true, false>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
-    return launch_t<TC, false, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, s);
+        return launch_t<TC, true, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, flag, s);
+    if (layers == SR_SL)
+        return launch_t<TC, true, false>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, flag, s);
+    return launch_t<TC, false, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, flag, s);
 }
 
 // Far field added to outputs that already hold the near sums, the extrapolation and the jump term
@@ -863,9 +880,10 @@ hipError_t dispatch(int layers, const SrcRec<double> *rec64, const Pos4<TC> *pos
 // extrapolation weights w = e_1^T A^{-1} of eq. (extrap_eqn) satisfy w A = e_1^T and the first column
 // of A is all ones, so they sum to one (up to rounding) and the far sum shared by the three smoothing
 // lengths enters once, unweighted: u += S_far / (8 pi), v += -6 T_far / (8 pi); a target with the
-// modified smoothing has the single weight 1.  One lane per (channel, target), channel-major, so
+// modified smoothing has the single weight 1.  STORE: u = S_far / (8 pi), v = -6 T_far / (8 pi) (the
+// plain sums at targets with no closest point).  One lane per (channel, target), channel-major, so
 // that the partial sums part[split][channel][target] are read coalesced and the grid fills the chip.
-template <bool SL, bool DL>
+template <bool SL, bool DL, bool STORE>
 __global__ __launch_bounds__(kBlock) void far_add_kernel(const double *__restrict__ part, int nparts, int64_t m,
                                                          double *__restrict__ u, double *__restrict__ v)
 {
@@ -877,36 +895,59 @@ __global__ __launch_bounds__(kBlock) void far_add_kernel(const double *__restric
     double far = 0.0;
     for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + c) * (size_t)m + t];
     const double inv8pi = 1.0 / (8.0 * kPi);
-    if (c < 3)
-        u[3 * t + c] += far * inv8pi;
-    else
-        v[3 * t + c - 3] += -6.0 * far * inv8pi;
+    double *o = c < 3 ? &u[3 * t + c] : &v[3 * t + c - 3];
+    const double val = (c < 3 ? far : -6.0 * far) * inv8pi;
+    *o = STORE ? val : *o + val;
+}
+
+__global__ void flag_clear_kernel(NearFlag *flag)
+{
+    if (threadIdx.x == 0) {
+        flag->bits = 0u;
+        flag->first = ~0ull;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, hipStream_t s)
+template <bool STORE>
+void launch_far_add_t(int layers, const double *part, int nparts, const EvalArgs &a, dim3 grid, hipStream_t s)
+{
+    const dim3 block(kBlock);
+    if (layers == (SR_SL | SR_DL))
+        hipLaunchKernelGGL((far_add_kernel<true, true, STORE>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+    else if (layers == SR_SL)
+        hipLaunchKernelGGL((far_add_kernel<true, false, STORE>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+    else
+        hipLaunchKernelGGL((far_add_kernel<false, true, STORE>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+}
+
+hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, bool store, hipStream_t s)
 {
     const int64_t lanes = (layers == (SR_SL | SR_DL) ? 6 : 3) * a.m;
-    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock)), block(kBlock);
-    if (layers == (SR_SL | SR_DL))
-        hipLaunchKernelGGL((far_add_kernel<true, true>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
-    else if (layers == SR_SL)
-        hipLaunchKernelGGL((far_add_kernel<true, false>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+    const dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock));
+    if (store)
+        launch_far_add_t<true>(layers, part, nparts, a, grid, s);
     else
-        hipLaunchKernelGGL((far_add_kernel<false, true>), grid, block, 0, s, part, nparts, a.m, a.u, a.v);
+        launch_far_add_t<false>(layers, part, nparts, a, grid, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_clear(NearFlag *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(flag_clear_kernel, dim3(1), dim3(kWave), 0, s, flag);
     return hipGetLastError();
 }
 
 hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> *rec64,
                                 const Pos4<double> *pos64, const Pos4<float> *pos32, const int *cell_start,
                                 const CellGrid &grid, const EvalArgs &a, const DevParams &p, const double *part,
-                                int nparts, hipStream_t s)
+                                int nparts, NearFlag *flag, hipStream_t s)
 {
     const double rc2 = p.rnear * p.rnear;
     if (precision == SR_MIXED)
-        return dispatch<float>(layers, rec64, pos32, cell_start, grid, a, p, (float)rc2, part, nparts, s);
-    return dispatch<double>(layers, rec64, pos64, cell_start, grid, a, p, rc2, part, nparts, s);
+        return dispatch<float>(layers, rec64, pos32, cell_start, grid, a, p, (float)rc2, part, nparts, flag, s);
+    return dispatch<double>(layers, rec64, pos64, cell_start, grid, a, p, rc2, part, nparts, flag, s);
 }
 
 }  // namespace sr

@@ -84,6 +84,36 @@ class Evaluator:
         B.sr_eval(self.ctx, layers, y, x0, n0, b, f0, q0, u, v, ud, vd, stream)
         return (u, v, ud, vd) if want_delta else (u, v)
 
+    def eval_far(self, layers: int, y, stream=None, out=None):
+        """Plain sums at targets with no closest point; returns (u, v) (None for a layer not asked for).
+        A target within the near radius of a source is reported by check()."""
+        import torch
+
+        m = int(y.shape[0])
+        kw = dict(dtype=torch.float64, device=y.device)
+        if out is not None:
+            u, v = out
+        else:
+            u = torch.empty((m, 3), **kw) if layers & B.SR_SL else None
+            v = torch.empty((m, 3), **kw) if layers & B.SR_DL else None
+        B.sr_eval_far(self.ctx, layers, y, u, v, stream)
+        return u, v
+
+    def eval_host(self, layers: int, y, x0, n0, b, f0=None, q0=None):
+        """sr_eval on host (numpy) arrays; returns numpy (u, v)."""
+        import numpy as np
+
+        m = int(y.shape[0])
+        u = np.empty((m, 3)) if layers & B.SR_SL else None
+        v = np.empty((m, 3)) if layers & B.SR_DL else None
+        c = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+        B.sr_eval_host(self.ctx, layers, c(y), c(x0), c(n0), c(b), c(f0), c(q0), u, v)
+        return u, v
+
+    def check(self, stream=None) -> None:
+        """Raises SrError (SR_ENEAR) if a target treated as far lay within the near radius of a source."""
+        B.sr_check(self.ctx, stream)
+
 
 class RigidSpheres:
     """Rigid spheres in Stokes flow (completed double layer, GMRES); thin wrapper of sr_rigid_*."""

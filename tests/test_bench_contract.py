@@ -19,4 +19,4 @@ def test_recorded_far_traffic_belongs_to_the_committed_kernel():
     sys.path.insert(0, ROOT)
     import bench
 
-    assert bench.far_traffic() is not None
+    assert bench.far_traffic("fp64") is not None and bench.far_traffic("mixed") is not None

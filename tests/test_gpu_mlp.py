@@ -214,3 +214,37 @@ def test_refined_solve_rejects_useless_guess(P):
     assert rr1 <= 1e-8 and rr2 <= 1e-8 and it1 == it0 and it2 == it0
     assert torch.equal(q0, q1) and torch.equal(q0, q2)
     R.close()
+
+
+def test_real_head_shape_matches_oracle(P):
+    """The network at its real shape: width 256, 102420 outputs (the two h = 1/32 spheres' unknowns),
+    batch 64.  The head's backward product dz = dout Wh then contracts over 102420 outputs and takes the
+    explicit K split of the GEMM (200 partial products summed in a fixed order) that the small shapes
+    above never reach.  Forward, every gradient block and one Adam step against the FP64 oracle."""
+    width, nout, batch = 256, 102420, 64
+    net, p, g, m, y = setup_net(P, width, nout, batch, 3, seed=21)
+    yd = to_dev(y)
+    net.fit_output_scale(yd)
+    s = net.output_scale().cpu().numpy()
+    o_gpu = net.forward(to_dev(g), to_dev(m)).cpu().numpy()
+    o, cache = omlp.forward(p, g, m, GMID, GHALF)
+    e = np.abs(o_gpu - o).max() / np.abs(o).max()
+    print(f"real shape forward: {e:.3e}", flush=True)
+    assert e <= 1e-4
+    grad, loss = net.gradients(to_dev(g), to_dev(m), yd)
+    t = y / s
+    gr = omlp.backward(p, cache, o, t)
+    assert abs(loss - omlp.loss(o, t)) <= 1e-5 * omlp.loss(o, t)
+    gg = unflat(grad.cpu().numpy(), width, nout)
+    for k in omlp.NAMES:
+        e = np.linalg.norm(gg[k] - gr[k]) / max(np.linalg.norm(gr[k]), 1e-30)
+        print(f"real shape grad {k}: {e:.2e}", flush=True)
+        assert e <= 1e-3, k
+    lr = 1e-3
+    net.train_step(to_dev(g), to_dev(m), yd, lr)
+    after = net.get_params().astype(np.float64)
+    ref = omlp.Adam(lr=lr).step({k: v.copy() for k, v in p.items()}, gg)
+    d = np.abs(after - flat(ref)).max()
+    print(f"real shape adam step: {d:.2e}", flush=True)
+    assert d <= 1e-3 * lr + 1e-6
+    net.close()

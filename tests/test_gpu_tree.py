@@ -195,3 +195,25 @@ def test_tree_work_counts(P, small, p, theta, leaf):
     assert (npx, nlf, ncl) == ref
     assert ncl + nlf == t.m * s.n
     assert npx % (p + 1) ** 3 == 0
+
+
+@pytest.fixture(scope="module")
+def spheroid128():
+    return workload.build_config("table1", h=1 / 128)
+
+
+@pytest.mark.parametrize("precision,p,theta,leaf", [(1, 10, 0.6, 2000), (1, 12, 0.6, 2000), (0, 12, 0.6, 2000),
+                                                    (1, 8, 0.6, 4000), (1, 8, 0.6, 16000), (0, 8, 0.6, 16000),
+                                                    (1, 8, 0.4, 2000), (1, 8, 0.8, 2000)])
+def test_tree_sweep_configurations_match_oracle(P, spheroid128, precision, p, theta, leaf):
+    """The configurations of the treecode sweep (paper section 4.2: theta, N0 and p around theta 0.6,
+    N0 2000, p 8, on the h = 1/128 spheroid of Table 1, N = 112006), including the largest degrees and
+    leaves, against the oracle treecode on 150 sampled grid targets."""
+    cfg = spheroid128
+    rng = np.random.default_rng(p * 1000 + leaf + int(theta * 10))
+    idx = np.sort(rng.choice(cfg["targets"].m, 150, replace=False))
+    gu, gv = tree_eval(P, cfg, precision, p, theta, leaf, idx)
+    ou, ov = oracle.tree_cfg(cfg, idx, p=p, theta=theta, leaf=leaf)
+    e1, e2 = rel_err(gu, ou), rel_err(gv, ov)
+    print(f"sweep config p={p} theta={theta} N0={leaf} prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
+    assert e1 <= TOL[precision] and e2 <= TOL[precision]
