@@ -68,7 +68,7 @@ FAR_TRAFFIC = {"bytes": {"fp64": 1.066e8, "mixed": 1.018e8},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "54c490788c6d13c1bddc22e0c0d0bffb6743d877a57c73a5e3f9b3f09f5fb7d2",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "bd3ae02a39b7ba0fb5045799ae84db7f813ef252c3e3dcb545d48627b06f0837"}}
+                           "ba562170c46e4f2f61407191b957f0177e565e5e8d289a7dae96a18fbf4296ee"}}
 
 
 def far_traffic(precision):

@@ -159,6 +159,27 @@ sr_status sr_check(sr_ctx *c, void *stream);
 /* Largest number of targets (and of surface points) the evaluation calls accept: 2^28. */
 int64_t sr_max_targets(void);
 
+/* sr_eval for callers that cannot allocate device memory: code under HIP graph capture, serving loops
+ * that must not call hipMalloc, harnesses that forbid it.  The same evaluation as sr_eval (same
+ * kernels, same results) on DEVICE arrays, with no per-delta outputs and no SR_HOST; the far-field
+ * partial sums go to a static device array of SR_NOALLOC_SCRATCH_BYTES (48 MiB) that every GPU the
+ * library runs on holds until the process ends, instead of a context buffer.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).
+ *   m           0 <= m <= SR_NOALLOC_MAX_TARGETS (65536); SR_EINVAL beyond it.
+ *   other arguments as sr_eval.
+ * SR_ESTATE if the context's cell list and source records are not built for its current surface and
+ * parameters (one sr_eval call on the context builds them; a new surface or new h, rho, cutoff or
+ * precision needs another); SR_EINVAL if far_method is SR_TREE (the treecode is not supported).  A
+ * new density is packed into the existing records without allocation.  Profiling is ignored: the near
+ * field always runs concurrently on the context's stream, as in sr_eval.  The static array keeps the
+ * last call's contents and needs no clearing (every partial sum read is written by the same call);
+ * all calls on one GPU share it, so two calls that overlap in time on one GPU race, whatever their
+ * contexts and streams. */
+#define SR_NOALLOC_MAX_TARGETS 65536
+#define SR_NOALLOC_SCRATCH_BYTES (16 * 6 * 8 * SR_NOALLOC_MAX_TARGETS)
+sr_status sr_eval_noalloc(sr_ctx *c, int layers, int64_t m, const double *y, const double *x0, const double *n0,
+                          const double *b, const double *f0, const double *q0, double *u, double *v, void *stream);
+
 /* Per-phase timing.  While profiling is on, every sr_eval runs its phases one after the other on
  * its stream (not concurrently) and records HIP events around each: SR_PHASE_FAR (the far-field
  * sum) and SR_PHASE_NEAR (near regularized sums plus extrapolation).  sr_get_profile waits for the recorded events, writes the accumulated

@@ -21,7 +21,7 @@ _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR
 
 # every symbol the header declares; the CPU test-suite checks that the library exports each one
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
-           "sr_eval", "sr_eval_far", "sr_check", "sr_max_targets", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+           "sr_eval", "sr_eval_far", "sr_eval_noalloc", "sr_check", "sr_max_targets", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
            "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
            "sr_rigid_solve_refined", "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
            "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
@@ -66,6 +66,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_set_density.argtypes = [vp, C.c_int, vp, vp]
     L.sr_eval.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.sr_eval_far.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp]
+    L.sr_eval_noalloc.argtypes = [vp, C.c_int, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.sr_check.argtypes = [vp, vp]
     L.sr_max_targets.argtypes = []
     L.sr_max_targets.restype = i64
@@ -121,7 +122,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_version.argtypes = []
     L.sr_version.restype = C.c_char_p
     for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
-               "sr_eval_far", "sr_check", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+               "sr_eval_far", "sr_eval_noalloc", "sr_check", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
                "sr_rigid_set_params",
                "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_solve_refined",
                "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity"):
@@ -205,6 +206,22 @@ def sr_eval(ctx, layers: int, y, x0, n0, b, f0=None, q0=None, u=None, v=None, u_
                                              _ptr(n0, "n0", 3), _ptr(b, "b"), _ptr(f0, "f0"), _ptr(q0, "q0"),
                                              _ptr(u, "u"), _ptr(v, "v"), _ptr(u_delta, "u_delta"),
                                              _ptr(v_delta, "v_delta"), _stream(stream)))
+
+
+SR_NOALLOC_MAX_TARGETS = 65536
+
+
+def sr_eval_noalloc(ctx, layers: int, y, x0, n0, b, f0=None, q0=None, u=None, v=None, stream=None) -> None:
+    """sr_eval without device allocation (device tensors; at most SR_NOALLOC_MAX_TARGETS targets)."""
+    m = int(y.shape[0])
+    for name, t in (("x0", x0), ("n0", n0), ("f0", f0), ("q0", q0), ("u", u), ("v", v)):
+        if t is not None and tuple(t.shape) != (m, 3):
+            raise ValueError(f"sr_eval_noalloc: {name} must have shape ({m}, 3)")
+    if b.dim() != 1 or b.shape[0] != m:
+        raise ValueError(f"sr_eval_noalloc: b must have shape ({m},)")
+    _check("sr_eval_noalloc", load_library().sr_eval_noalloc(
+        ctx, int(layers), m, _ptr(y, "y", 3), _ptr(x0, "x0", 3), _ptr(n0, "n0", 3), _ptr(b, "b"), _ptr(f0, "f0"),
+        _ptr(q0, "q0"), _ptr(u, "u"), _ptr(v, "v"), _stream(stream)))
 
 
 def sr_eval_far(ctx, layers: int, y, u=None, v=None, stream=None) -> None:

@@ -43,21 +43,6 @@ sr_status fail(sr_status st, const char *fmt, ...)
                         hipGetErrorString(e_));                                                      \
     } while (0)
 
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
@@ -421,6 +406,12 @@ sr_status sr_create(sr_ctx **out, int device)
             delete c;
             return fail(SR_EHIP, "sr_create: stream or event creation failed: %s", hipGetErrorString(e));
         }
+        // the address of this device's static scratch array (sr_eval_noalloc), resolved once per device
+        e = noalloc_setup(device);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(SR_EHIP, "sr_create: cannot resolve the static scratch array: %s", hipGetErrorString(e));
+        }
         // the target-consistency report, cleared
         e = hipMalloc((void **)&c->flag, sizeof(NearFlag));
         if (e == hipSuccess) e = launch_flag_clear(c->flag, c->side);
@@ -702,6 +693,8 @@ sr_status sr::set_error(sr_status st, const char *msg)
 {
     return fail(st, "%s", msg);
 }
+
+void sr::clear_error() { g_err.clear(); }
 
 int sr::ctx_device(const sr_ctx *c) { return c->device; }
 

@@ -148,6 +148,26 @@ sr_status eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, const
                          double *u_delta, double *v_delta, hipStream_t s, double *ext_part);
 // Sets the thread's error message (sr_last_error) and returns st.
 sr_status set_error(sr_status st, const char *msg);
+// Clears the thread's error message (every entry point starts with it).
+void clear_error();
+// Makes `dev` the current device and restores the caller's on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+// Resolves the address of the current device's copy of the static scratch array of the
+// allocation-free evaluation (sr_noalloc.hip); called once per device by sr_create with that device
+// current.  Returns the error of hipGetSymbolAddress.
+hipError_t noalloc_setup(int device);
 // Device ordinal of a context.
 int ctx_device(const sr_ctx *c);
 

@@ -101,3 +101,20 @@ def test_single_precision_cell_margin_bound():
         true_r = np.linalg.norm(y - x, axis=1)
         assert near.any()
         assert (true_r[near] <= side).all(), (extent, true_r[near].max(), side)
+
+
+def test_noalloc_target_limit_checked_before_anything_else():
+    """sr_eval_noalloc rejects m above its static scratch capacity, host arrays (SR_HOST) and bad layers
+    before it looks at the context."""
+    lib = P.load_library()
+    cap = P.binding.SR_NOALLOC_MAX_TARGETS
+    nul = [None] * 9
+    assert lib.sr_eval_noalloc(None, P.SR_SL, cap + 1, *nul) == P.binding.SR_EINVAL
+    assert "out of range" in lib.sr_last_error().decode()
+    assert lib.sr_eval_noalloc(None, P.SR_SL | P.SR_HOST, 1, *nul) == P.binding.SR_EINVAL
+    assert "layers" in lib.sr_last_error().decode()
+    assert lib.sr_eval_noalloc(None, P.SR_DL, cap, *nul) == P.binding.SR_EINVAL
+    assert "ctx is NULL" in lib.sr_last_error().decode()
+    # the header's figures agree with the binding's
+    text = open(HEADER).read()
+    assert f"#define SR_NOALLOC_MAX_TARGETS {cap}" in text
