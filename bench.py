@@ -30,7 +30,7 @@ Other workloads (--workload; each prints its own JSON line):
              error against the FP64 direct sum.
   drops      the paper's two drops nearly touching (section 4.3): GMRES to 1e-10 at h = 1/16 ... 1/128,
              iterations, times and the self-convergence errors of Table 2.
-  peak       vector-ALU issue rates of the GPU (FP32 FMA unpacked, FP64 FMA, FP32 rsq).
+  peak       vector-ALU issue rates of the GPU (FP32 FMA with a scalar or only vector operands, FP64 FMA, FP32 rsq).
 """
 from __future__ import annotations
 
@@ -53,9 +53,10 @@ if ROOT not in sys.path:
 # and one DL pair per far target-source pair: 66 flops.
 FAR_FLOPS_SL, FAR_FLOPS_DL = 34, 32
 FAR_FLOPS_PER_PAIR_SLDL = FAR_FLOPS_SL + FAR_FLOPS_DL
-# MI355X published peaks (AMD): FP64 vector 78.6 TFLOP/s, FP32 vector 157.3 TFLOP/s (the latter with two
-# FP32 operations per lane and cycle, i.e. packed FP32, which this build does not use); the attainable
-# unpacked FP32 rate is measured by --workload peak and reported beside.
+# MI355X published peaks (AMD): FP64 vector 78.6 TFLOP/s, FP32 vector 157.3 TFLOP/s.  This build uses no
+# packed FP32 instructions; plain FP32 instructions whose operands are all vector registers issue at about
+# twice the rate of those with a scalar operand, which --workload peak measures (about 140 TFLOP/s) and the
+# line reports beside the published figure.
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_PUBLISHED_TFLOPS = 157.3
 PEAK_VALU_TFLOPS = PEAK_FP64_TFLOPS
@@ -64,9 +65,9 @@ TREE_FLOPS_PER_PROXY_PAIR = 75  # SL 24 + DL 40 + d, r^2, rsqrt, 1/r^2, 1/r^3 (1
 # HBM bytes per launch of the far-field kernels at this workload (FP64 and mixed), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).
 # Valid only for the kernel sources they were measured on: reported as null once a source's hash differs.
-FAR_TRAFFIC = {"bytes": {"fp64": 1.066e8, "mixed": 1.018e8},
+FAR_TRAFFIC = {"bytes": {"fp64": 1.068e8, "mixed": 9.786e7},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
-                           "54c490788c6d13c1bddc22e0c0d0bffb6743d877a57c73a5e3f9b3f09f5fb7d2",
+                           "6b086652b476622e8e98cd422ed0556afc7712d2b9cc2799d7b853a8ef3f544e",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
                            "ba562170c46e4f2f61407191b957f0177e565e5e8d289a7dae96a18fbf4296ee"}}
 
@@ -801,8 +802,8 @@ def near_pair_count(cfg):
 
 def peak_rates():
     """Measured vector-ALU rates from bench_peak.so (TFLOP/s, an FMA counting 2; rsq and add in Tops/s):
-    unpacked FP32 FMA (scalar and vector operands), FP64 FMA, FP32 rsq, FP32 and FP64 add; 2048
-    workgroups of 256 lanes, best of 4 launches."""
+    FP32 FMA with a scalar operand and with vector operands only, FP64 FMA, FP32 rsq, FP32 and FP64 add
+    (no packed FP32); 2048 workgroups of 256 lanes (8 wavefronts per SIMD), best of 4 launches."""
     import ctypes as C
 
     path = os.path.join(ROOT, "bench_peak.so")
@@ -812,8 +813,8 @@ def peak_rates():
     L.pk_run.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float)]
     L.pk_run.restype = C.c_double
     out = {}
-    for kind, name, iters in ((0, "fp32_fma_unpacked", 4096), (1, "fp64_fma", 2048), (2, "fp32_rsq", 2048),
-                              (3, "fp32_add", 4096), (4, "fp32_fma_unpacked_vector_operands", 4096),
+    for kind, name, iters in ((0, "fp32_fma_scalar_operand", 4096), (1, "fp64_fma", 2048), (2, "fp32_rsq", 2048),
+                              (3, "fp32_add_scalar_operand", 4096), (4, "fp32_fma_vector_operands", 4096),
                               (5, "fp64_add", 2048)):
         best = 0.0
         for _ in range(4):
@@ -828,9 +829,9 @@ def peak_rates():
 
 def bench_peak(a):
     r = peak_rates()
-    out = base_line("vector ALU issue rate (microbenchmark)", r["fp32_fma_unpacked"], "TFLOP/s", 4, 0, None, True,
-                    "f32", "synthetic (register-resident FMA / rsq chains)",
-                    {"workload": "2048 workgroups x 256 lanes, 16 independent chains per lane"})
+    out = base_line("vector ALU issue rate (microbenchmark)", r["fp32_fma_vector_operands"], "TFLOP/s", 4, 0, None,
+                    True, "f32", "synthetic (register-resident FMA / rsq chains)",
+                    {"workload": "2048 workgroups x 256 lanes, 8 or 16 independent chains per lane"})
     out["roofline"] = None
     out["rates"] = r
     out["published"] = {"fp64_vector": PEAK_FP64_TFLOPS, "fp32_vector_packed": PEAK_FP32_PUBLISHED_TFLOPS}
@@ -932,8 +933,8 @@ def bench_c2(a):
     def roofline(prec_name, peak, peak_name):
         far_ms = res[prec_name]["phases"][0]
         achieved = FAR_FLOPS_PER_PAIR_SLDL * far_pairs / (far_ms / 1e3) / 1e12
-        return {"bound": "alu", "kernel": f"far_direct_kernel<{'double' if prec_name == 'fp64' else 'float'}> "
-                "(far-field pair sum, single+double layer)", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        return {"bound": "alu", "kernel": ("far_direct_kernel<double>" if prec_name == "fp64" else "far_lds_kernel "
+                "(single precision)") + " (far-field pair sum, single+double layer)", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "peak_is": peak_name, "traffic": far_traffic(prec_name),
                 "traffic_unit": "bytes per launch (HBM, counters scaled by a copy calibration)",
                 "flops_per_pair": FAR_FLOPS_PER_PAIR_SLDL, "far_pairs_per_launch": far_pairs,
@@ -962,7 +963,7 @@ def bench_c2(a):
                      "ms_per_step_phases_serial": r["serial_ms"], "setup_ms": setup[name]}
     mixed_rf = roofline("mixed", PEAK_FP32_PUBLISHED_TFLOPS, "published FP32 vector (packed)")
     if peaks:
-        mixed_rf["frac_of_measured_unpacked_fp32"] = mixed_rf["achieved"] / peaks["fp32_fma_unpacked"]
+        mixed_rf["frac_of_measured_fp32_vector_operands"] = mixed_rf["achieved"] / peaks["fp32_fma_vector_operands"]
     out["mixed"]["roofline"] = mixed_rf
     out["vector_alu_measured_tflops"] = peaks
     if not a.no_gmres:
