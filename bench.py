@@ -69,7 +69,7 @@ FAR_TRAFFIC = {"bytes": {"fp64": 1.068e8, "mixed": 9.786e7},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "6b086652b476622e8e98cd422ed0556afc7712d2b9cc2799d7b853a8ef3f544e",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "ba562170c46e4f2f61407191b957f0177e565e5e8d289a7dae96a18fbf4296ee"}}
+                           "d3240416bf69c70873bd45e37c52add3523e6d799bd649ea616ebfc66be94756"}}
 
 
 def far_traffic(precision):

@@ -175,11 +175,19 @@ double near_radius(const sr_params &p)
     return p.cutoff * r * p.h;
 }
 
-// Uniform grid of cells of side >= the near radius plus a margin, so that every pair the near test
-// calls near lies in neighbouring cells; sources sorted by cell with a stable counting sort.  The
+// The reach of a near radius: every pair that the near test calls near is truly closer than it.  The
 // single-precision test rounds each coordinate relative to org (error <= 2^-24 |x - org| per
 // coordinate, and as much again in the difference and the sum of squares), so the margin grows with
 // the extent E of the points: 4 * 2^-24 * (2 E + rnear) on the mixed path, plus a relative 1e-5.
+double reach_of(const sr_ctx *c, double radius, double rnear)
+{
+    double r = radius * (1.0 + 1e-5);
+    if (c->prm.precision == SR_MIXED) r += 4.0 * std::ldexp(1.0, -24) * (2.0 * c->extent + rnear);
+    return r;
+}
+
+// Uniform grid of cells of side reach / kCellsPerReach (larger only when the grid would exceed
+// kMaxCells cells); sources sorted by cell with a stable counting sort.
 sr_status build_layout(sr_ctx *c, hipStream_t s)
 {
     const double rnear = near_radius(c->prm);
@@ -194,8 +202,7 @@ sr_status build_layout(sr_ctx *c, hipStream_t s)
             lo[d] = std::min(lo[d], c->hx[3 * i + d]);
             hi[d] = std::max(hi[d], c->hx[3 * i + d]);
         }
-    double side = rnear * (1.0 + 1e-5);
-    if (c->prm.precision == SR_MIXED) side += 4.0 * std::ldexp(1.0, -24) * (2.0 * c->extent + rnear);
+    double side = reach_of(c, rnear, rnear) / kCellsPerReach;
     const int64_t kMaxCells = int64_t(1) << 22;
     int g[3];
     for (;;) {
@@ -236,6 +243,7 @@ sr_status build_layout(sr_ctx *c, hipStream_t s)
         c->grid.lo[d] = lo[d];
         c->grid.g[d] = g[d];
     }
+    c->grid.side = side;
     c->grid.inv_side = inv_side;
     c->grid_rnear = rnear;
     c->grid_precision = c->prm.precision;
@@ -597,6 +605,8 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
     dp.sharp = c->prm.surface_sharp ? 1 : 0;
     dp.inv_dsharp = 1.0 / (c->prm.sharp_rho * c->prm.h);
     dp.rsharp = dp.sharp ? std::min(dp.rnear, c->prm.cutoff * c->prm.sharp_rho * c->prm.h) : dp.rnear;
+    dp.reach = reach_of(c, dp.rnear, dp.rnear);
+    dp.reach_sharp = reach_of(c, dp.rsharp, dp.rnear);
 
     const bool tree = c->prm.far_method == SR_TREE;
     int nparts = kFarSplits;

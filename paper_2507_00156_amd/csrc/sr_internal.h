@@ -58,11 +58,15 @@ __device__ __forceinline__ double pair_r2(double yx, double yy, double yz, doubl
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
 }
 
-// Uniform cell grid over the sources (side >= near radius): cells in x-major, z-fastest order;
-// sources are stored sorted by cell, cell c owning records [cell_start[c], cell_start[c+1]).
+// Uniform cell grid over the sources: cells in x-major, z-fastest order; sources are stored sorted by
+// cell, cell c owning records [cell_start[c], cell_start[c+1]).  The side is a third of the near
+// radius plus its rounding margin (the reach), so the near pairs of a target lie in the cells within
+// the reach of it: about 7 x 7 columns of 7 cells, of which the near-field kernel skips the columns
+// whose box lies beyond the reach.
+constexpr int kCellsPerReach = 3;
 struct CellGrid {
     double lo[3];
-    double inv_side;
+    double side, inv_side;
     int g[3];
 };
 
@@ -103,6 +107,9 @@ struct DevParams {
     double rnear;        // cutoff * max_j delta_j (and the modified-smoothing delta if larger)
     double rflag;        // a target with |b| >= cutoff * max_j delta_j and a source closer than this is
                          // reported (kFlagFarRule): cutoff * max_j delta_j less a rounding margin
+    double reach;        // rnear plus the rounding margin of the pair test: every pair that test calls
+                         // near is truly closer than this
+    double reach_sharp;  // the same for the near radius rsharp of the surface targets (modified smoothing)
     int precision;
     int pow234;          // the sorted deltas are in the ratio 2 : 3 : 4 (exp(-t_j^2) by powers of one exp)
     int sharp;           // targets on the surface (b == 0) use the modified smoothing at one delta

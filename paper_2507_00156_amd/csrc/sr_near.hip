@@ -17,21 +17,25 @@
 // coincide and w = (1, 0, 0) (the matrix is numerically singular there).
 // Double layer: + chi q0 with chi = 1, 0, 1/2 for b < 0, b > 0, b == 0 (eq. (Stokes_DL1)).
 //
-// Work decomposition: one wavefront per target (4 per workgroup).  The target's cell and its
-// neighbours in the uniform cell grid (side >= near radius) hold every near pair; with cells in
-// z-fastest order, the 27 neighbour cells are 9 contiguous ranges.  The 64 lanes test candidates 64 at
-// a time (compact single- or double-precision positions; several such loads in flight per wavefront)
-// and append the near ones to a per-wave ring buffer in LDS; each time it holds 64 pairs, all 64 lanes
-// evaluate one pair each, so the FP64 regularized kernels run without idle lanes.  The three smoothing
-// factors of a pair share one exp(-t^2) and one polynomial (no branches): s_k = 1 - exp(-t^2) P_k(t)
-// with P_1 = erfcx(t), P_2 = P_1 + (2/sqrt(pi)) t, P_3 = P_2 + (4/(3 sqrt(pi))) t^3.
-// When only the extrapolated values are asked for, the weights w_j are computed first and a pair
-// adds K(S), S_k = sum_j w_j s_k(t_j), to one set of accumulators (the kernels are linear in s_k).
-// A batch of 64 pairs skips a smoothing length when none of its pairs lies within that length's
-// cut-off ball (a wavefront-uniform test).  Skipping per pair would save about 40% of the smoothing
-// work, but it needs pairs sorted into per-class queues so that a batch of 64 shares its class;
-// measured on MI355X, the queue bookkeeping cost more than the smoothing it saved (per-class queues:
-// 27% fewer FP64 FMAs, 19% more VALU instructions in all).
+// Work decomposition: one wavefront per target (4 per workgroup).  The cell grid's side is a third
+// of the reach (the near radius plus its rounding margin), so the target's near pairs lie in the
+// columns of cells within the reach: up to 7 x 7 columns, each a contiguous record range of the cells
+// within the reach in z.  The lanes set up the columns in parallel (one per lane: the column is
+// dropped when its xy-box lies beyond the reach, else its range is loaded), then the wavefront scans
+// the live columns: the lanes test candidates 64 at a time (compact single- or double-precision
+// positions; up to kDepth loads in flight, only the steps that hold candidates) and append the near
+// ones to a per-wave ring buffer in LDS; each time it holds 64 pairs, all 64 lanes evaluate one pair
+// each, so the FP64 regularized kernels run without idle lanes.
+// Smoothing factors: s1 = 1 - E R, s2 = 1 - E P2, s2 - s3 = (4/(3 sqrt(pi))) t^3 E with E = e^{-t^2},
+// R = erfcx(t) (sr_erfcx_table.h), P2 = R + (2/sqrt(pi)) t; with rho in the ratio 2 : 3 : 4 the three
+// exponentials are powers of one.  When only the extrapolated values are asked for, the weights w_j
+// are computed first and a pair adds K(S), S_k = sum_j w_j s_k(t_j), to one set of accumulators (the
+// kernels are linear in the factors).  A batch of 64 pairs skips a smoothing length when none of its
+// pairs lies within that length's cut-off ball (a wavefront-uniform test; beyond it the factors are 1).
+// The double layer is summed as d (...) plus n0 (...), the n0 part as one scalar per target (see
+// add_terms).  The closest pairs (r < kSeriesT max delta, the target's own point included) are left
+// out of this pass and added by an exact pass (Maclaurin series of the factors where t < kSeriesT; the
+// r -> 0 limits) run only on the lanes that hold them.
 // Per-lane FP64 partial sums are combined by a butterfly wavefront reduction.
 // A target whose |b| selects w = (1, 0, 0) lies, by its own b, at least cutoff * max delta from the
 // surface; if a source is closer than that (less a rounding margin) the caller's b is wrong and the
@@ -45,25 +49,11 @@
 
 namespace sr {
 
-// The erfcx coefficients as device variables with external linkage: the compiler cannot fold them
-// into immediates, so the polynomial reads them with scalar loads into SGPRs instead of keeping 17
-// FP64 constants (34 VGPRs) live across the pair loop.  Two tables: degree 16 (|erfc error| ~6e-16)
-// for the double-precision path, degree 11 (~2e-11) for the mixed-precision path, whose
-// single-precision far field (relative error ~1e-7) dominates its error; 5 fewer FMAs per
-// smoothing evaluation and 10 fewer scalar registers.
-template <class EP>
-struct ErfcxCoef {
-    double c[EP::kDegree + 1];
-};
-template <class EP>
-constexpr ErfcxCoef<EP> make_erfcx_coef()
-{
-    ErfcxCoef<EP> r{};
-    for (int k = 0; k <= EP::kDegree; ++k) r.c[k] = EP::kC[k];
-    return r;
-}
-__constant__ ErfcxCoef<erfcx_poly::Fp64> g_erfcx_coef = make_erfcx_coef<erfcx_poly::Fp64>();
-__constant__ ErfcxCoef<erfcx_poly::Mixed> g_erfcx_coef_mixed = make_erfcx_coef<erfcx_poly::Mixed>();
+// The erfcx coefficients live in device variables with external linkage: the compiler cannot fold
+// them into immediates, so the polynomial reads them with scalar loads into SGPRs instead of keeping
+// 17 FP64 constants (34 VGPRs) live across the pair loop.  Two tables: degree 16 (|erfc error|
+// ~6e-16) for the double-precision path, degree 11 (~2e-11) for the mixed-precision path, whose
+// single-precision far field (relative error ~1e-7) dominates its error.
 
 namespace {
 
@@ -98,6 +88,51 @@ __device__ __forceinline__ double I2f(double lam)
     return (2.0 / 3.0) * ((0.5 - lam * lam) * exp(-lam * lam) * kInvSqrtPi + a * a * a * erfc(a));
 }
 
+// acc * x + c as one fused multiply-add with the coefficient c in a scalar register.  Written out
+// because the compiler otherwise keeps the polynomial coefficients in vector registers and, to use
+// its two-address multiply-add, copies the coefficient into the destination before every step (one
+// extra instruction per coefficient and about 50 more VGPRs for the kernel).
+__device__ __forceinline__ double fma_coef(double acc, double x, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(acc), "v"(x), "s"(c));
+    return r;
+}
+
+// e^x for x <= 0 by Cody and Waite's reduction (W. J. Cody, W. Waite, Software Manual for the
+// Elementary Functions, 1980): x = k ln2 + f with k = rint(x / ln2), |f| <= ln2/2, ln2 split into a
+// 32-bit head (k ln2_hi exact for |k| < 2^21) and a tail; e^f by its Taylor polynomial of degree 13
+// (remainder below 5e-18 relative), e^x = 2^k e^f (0 once 2^k underflows).  Written as plain Horner
+// steps so that no coefficient register is overwritten (no copies), with no range checks: the callers'
+// arguments are finite and non-positive.
+struct ExpTaylor {
+    double c[14];
+};
+constexpr ExpTaylor make_exp_taylor()
+{
+    ExpTaylor r{};
+    double f = 1.0;
+    for (int n = 0; n < 14; ++n) {
+        r.c[n] = 1.0 / f;  // 1/n!, n! exact in double for n <= 18
+        f *= (double)(n + 1);
+    }
+    return r;
+}
+constexpr ExpTaylor kExpTaylor = make_exp_taylor();
+constexpr double kLn2Hi = 0.6931471803691238;      // ln 2 to 32 bits
+constexpr double kLn2Lo = 1.9082149292705877e-10;  // ln 2 - kLn2Hi
+constexpr double kLog2E = 1.4426950408889634;
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    const double k = __builtin_rint(x * kLog2E);
+    double f = __builtin_fma(-k, kLn2Hi, x);
+    f = __builtin_fma(-k, kLn2Lo, f);
+    double p = kExpTaylor.c[13];
+#pragma unroll
+    for (int n = 12; n >= 0; --n) p = fma_coef(p, f, kExpTaylor.c[n]);
+    return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
 // Maclaurin coefficients for t < kSeriesT: s1 = c t sum A1_n t^2n, s2 = c t^3 sum A2_n t^2n,
 // s3 = c t^5 sum A3_n t^2n (c = 2/sqrt(pi)), with A1_n = (-1)^n / (n! (2n+1)),
 // A2_n = (-1)^n 2 / (n! (2n+3)), A3_n = (-1)^n 4 / (3 n! (2n+5)) (series of erf and exp).
@@ -126,6 +161,26 @@ __constant__ constexpr SeriesCoef kSeries = make_series();
 // keep the relative accuracy of s2 ~ t^3 and s3 ~ t^5 that the differences below would lose).
 // erfcx(t) for 0 <= t <= 6.25 from the interpolating polynomial of sr_erfcx_table.h: the degree-16
 // table, or with LO the mixed-precision path's degree-11 table.
+// The table's coefficients times L, so that erfcx = inv * P_L(x) with one product.
+template <class EP>
+struct ErfcxCoefL {
+    double c[EP::kDegree + 1];
+};
+template <class EP>
+constexpr ErfcxCoefL<EP> make_erfcx_coef_l()
+{
+    ErfcxCoefL<EP> r{};
+    for (int k = 0; k <= EP::kDegree; ++k) r.c[k] = EP::kL * EP::kC[k];
+    return r;
+}
+__constant__ ErfcxCoefL<erfcx_poly::Fp64> g_erfcx_coef_l = make_erfcx_coef_l<erfcx_poly::Fp64>();
+__constant__ ErfcxCoefL<erfcx_poly::Mixed> g_erfcx_coef_mixed_l = make_erfcx_coef_l<erfcx_poly::Mixed>();
+
+// erfcx(t), t >= 0, from the interpolating polynomial of sr_erfcx_table.h in the variable
+// x = A (t - L)/(t + L) + B = (A + B) - 2 A L inv, inv = 1/(t + L): erfcx = inv * sum_k (L C_k) x^k.
+// The reciprocal is the hardware estimate refined by Newton steps y <- y + y (1 - den y): two for
+// the degree-16 table (full double precision), one for the mixed path's degree-11 table (relative
+// error ~1e-15, far below that table's 2e-11).  Accurate on [0, 6.25]; finite for every t >= 0.
 template <bool LO>
 __device__ __forceinline__ double erfcx_eval(double tc)
 {
@@ -134,35 +189,22 @@ __device__ __forceinline__ double erfcx_eval(double tc)
     double inv = __builtin_amdgcn_rcp(den);
     double e = __builtin_fma(-den, inv, 1.0);
     inv = __builtin_fma(inv, e, inv);
-    e = __builtin_fma(-den, inv, 1.0);
-    inv = __builtin_fma(inv, e, inv);
-    const double x = __builtin_fma(EP::kA, (tc - EP::kL) * inv, EP::kB);
+    if (!LO) {
+        e = __builtin_fma(-den, inv, 1.0);
+        inv = __builtin_fma(inv, e, inv);
+    }
+    const double x = __builtin_fma(-2.0 * EP::kA * EP::kL, inv, EP::kA + EP::kB);
     double pz;
     if constexpr (LO) {
-        pz = g_erfcx_coef_mixed.c[EP::kDegree];
+        pz = g_erfcx_coef_mixed_l.c[EP::kDegree];
 #pragma unroll
-        for (int k = EP::kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef_mixed.c[k]);
+        for (int k = EP::kDegree - 1; k >= 0; --k) pz = fma_coef(pz, x, g_erfcx_coef_mixed_l.c[k]);
     } else {
-        pz = g_erfcx_coef.c[EP::kDegree];
+        pz = g_erfcx_coef_l.c[EP::kDegree];
 #pragma unroll
-        for (int k = EP::kDegree - 1; k >= 0; --k) pz = __builtin_fma(pz, x, g_erfcx_coef.c[k]);
+        for (int k = EP::kDegree - 1; k >= 0; --k) pz = fma_coef(pz, x, g_erfcx_coef_l.c[k]);
     }
-    return EP::kL * inv * pz;
-}
-
-// erfc(t) = exp(-t^2) erfcx(t) (|erfc error| < 1e-15 on [0, 6.25] with the degree-16 table, 2e-11 with
-// LO); beyond 6.25 exp(-t^2) < 1e-16 makes the clamped erfcx value irrelevant.
-template <bool LO>
-__device__ __forceinline__ void smoothing3(double t, double E, double cutoff, double &s1, double &s2, double &s3)
-{
-    const double R = erfcx_eval<LO>(fmin(t, 6.25));
-    const double P2 = __builtin_fma(kTwoOverSqrtPi, t, R);
-    const double P3 = __builtin_fma((2.0 / 3.0) * kTwoOverSqrtPi * t * t, t, P2);
-    const double Ec = t > cutoff ? 0.0 : E;  // beyond the cut-off s1 = s2 = s3 = 1 exactly
-    const bool ser = t < kSeriesT;
-    s1 = ser ? 0.0 : __builtin_fma(-Ec, R, 1.0);
-    s2 = ser ? 0.0 : __builtin_fma(-Ec, P2, 1.0);
-    s3 = ser ? 0.0 : __builtin_fma(-Ec, P3, 1.0);
+    return inv * pz;
 }
 
 // s1, s2, s3 for t < kSeriesT from their Maclaurin series.
@@ -189,7 +231,7 @@ __device__ __forceinline__ void series3(double t, double &s1, double &s2, double
 template <bool LO>
 __device__ __forceinline__ void smoothing3_sharp(double t, double cutoff, double &s1, double &s2, double &s3)
 {
-    const double E = exp(-t * t);
+    const double E = exp_nonpos(-t * t);
     const double R = erfcx_eval<LO>(fmin(t, 6.25));
     const double t2 = t * t, c3 = kTwoOverSqrtPi / 3.0, c9 = kTwoOverSqrtPi / 9.0;
     const double P1 = R - c3 * t * __builtin_fma(-2.0, t2, 5.0);
@@ -244,394 +286,294 @@ __device__ __forceinline__ void series3_sharp(double t, double &s1, double &s2, 
 
 __device__ __forceinline__ double pick3(const double (&v)[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
 
-struct Target {
-    double y[3], x0[3], n[3], b, c, q0[3];
-    double w[3];  // extrapolation weights (sorted-delta order), used when the sums are combined
+// Target data used by the pair evaluation (wavefront-uniform values; see to_vgpr for where they are
+// held).
+struct TgtV {
+    double y[3], n[3], q0[3], b, c;
+    double w[3];  // extrapolation weights (sorted-delta order)
 };
 
-struct Acc {
-    double sl[3][3], dl[3][3];
+// Per-lane accumulators: slot 0 for the combined sums, slots 0..2 per delta otherwise.
+template <int NJ>
+struct AccN {
+    double sl[NJ][3], dl[NJ][3];
+    double dn[NJ];  // double layer: the scalar factor of n0 (see add_terms)
 };
 
-// Adds one pair's contribution with smoothing factors s1, s2, s3 at sorted position J.
-// COMB: the extrapolation weight w_J is applied here and every delta adds into slot 0 (one set of
-// accumulators: sum_j w_j (far + near_j) = far + sum_j w_j near_j since the weights sum to 1).
-template <int J, bool SL, bool DL, bool COMB>
-__device__ __forceinline__ void add_delta(double s1, double s2, double s3, double ir, double ir3, double ir5,
-                                          double dx, double dy, double dz, double gx, double gy, double gz,
-                                          double dg, double t1x, double t1y, double t1z, double ex, double ey,
-                                          double ez, double wJ, Acc &A)
+// s2 - s3 = (4 / (3 sqrt(pi))) t^3 e^{-t^2} (from P_3 = P_2 + (4 / (3 sqrt(pi))) t^3)
+constexpr double kD3 = 2.0 / 3.0 * kTwoOverSqrtPi;
+
+// 1/sqrt(v), v > 0 finite: hardware estimate and two Newton steps y <- y + (y/2)(1 - v y^2)
+__device__ __forceinline__ double rsq64(double v)
 {
-    constexpr int K = COMB ? 0 : J;
-    if (COMB) {
-        s1 *= wJ;
-        s2 *= wJ;
-        s3 *= wJ;
-    }
-    if (SL) {
-        const double k1 = s1 * ir, k2 = dg * s2 * ir3;
-        A.sl[K][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[K][0]));
-        A.sl[K][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[K][1]));
-        A.sl[K][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[K][2]));
-    }
-    if (DL) {
-        const double k2 = s2 * ir3, k3 = s3 * ir5;
-        A.dl[K][0] = __builtin_fma(ex, k3, __builtin_fma(t1x, k2, A.dl[K][0]));
-        A.dl[K][1] = __builtin_fma(ey, k3, __builtin_fma(t1y, k2, A.dl[K][1]));
-        A.dl[K][2] = __builtin_fma(ez, k3, __builtin_fma(t1z, k2, A.dl[K][2]));
-    }
+    double y = __builtin_amdgcn_rsq(v);
+    double e = __builtin_fma(-(v * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-(v * y), y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
 }
 
-template <int J, bool SL, bool DL, bool COMB, bool LO>
-__device__ __forceinline__ void accumulate_delta(double r, double E, double ir, double ir3, double ir5, double dx,
-                                                 double dy, double dz, double gx, double gy, double gz, double dg,
-                                                 double t1x, double t1y, double t1z, double ex, double ey, double ez,
-                                                 const DevParams &p, const Target &T, Acc &A)
+// e^{-t_j^2} for the three sorted deltas: with P234 (deltas in the ratio 2 : 3 : 4) B^36, B^16, B^9 of
+// B = e^{-(t_0/6)^2}, one exponential and seven products (relative error ~50 ulp); otherwise three
+// exponentials.
+template <bool P234>
+__device__ __forceinline__ void exp3(double r, const DevParams &p, double &E0, double &E1, double &E2)
 {
-    double s1, s2, s3;
-    smoothing3<LO>(r * p.inv_delta[J], E, p.cutoff, s1, s2, s3);
-    add_delta<J, SL, DL, COMB>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                               T.w[J], A);
-}
-
-// The contributions that smoothing3 left out (t < kSeriesT), from the series.  Rarely executed: only
-// pairs closer than kSeriesT times the largest delta reach it.
-template <int J, bool SL, bool DL, bool COMB>
-__device__ __forceinline__ void series_delta(double r, double ir, double ir3, double ir5, double dx, double dy,
-                                             double dz, double gx, double gy, double gz, double dg, double t1x,
-                                             double t1y, double t1z, double ex, double ey, double ez,
-                                             const DevParams &p, const Target &T, Acc &A)
-{
-    const double t = r * p.inv_delta[J];
-    if (t < kSeriesT) {
-        double s1, s2, s3;
-        series3(t, s1, s2, s3);
-        add_delta<J, SL, DL, COMB>(s1, s2, s3, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                   T.w[J], A);
-    }
-}
-
-// One near pair, accumulated at the three smoothing lengths (sorted-delta order).  SER = false: the
-// closed-form smoothing factors, leaving out t < kSeriesT; returns whether some t is below kSeriesT
-// (then the caller calls it again with SER = true, which adds just those terms from the series).
-template <bool SL, bool DL, bool SER, bool P234, bool COMB, bool LO>
-__device__ __forceinline__ bool near_pair(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
-{
-    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 == 0.0) {
-        if (SER) return false;
-        // target on a quadrature point: limit of s1(r/delta)/r is 2/(sqrt(pi) delta); the d d s2/r^3
-        // term and the whole double-layer term vanish
-        if (SL) {
-            const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const double l = kTwoOverSqrtPi * p.inv_delta[j] * (COMB ? T.w[j] : 1.0);
-                const int k = COMB ? 0 : j;
-                A.sl[k][0] += gx * l;
-                A.sl[k][1] += gy * l;
-                A.sl[k][2] += gz * l;
-            }
-        }
-        return false;
-    }
-    const double ir = rsqrt(r2);
-    const double r = r2 * ir;
-    const double ir2 = ir * ir;
-    const double ir3 = ir2 * ir;
-    const double ir5 = ir3 * ir2;
-    double gx = 0, gy = 0, gz = 0, dg = 0;
-    if (SL) {
-        gx = s.fw[0] - T.c * s.nw[0];
-        gy = s.fw[1] - T.c * s.nw[1];
-        gz = s.fw[2] - T.c * s.nw[2];
-        dg = dx * gx + dy * gy + dz * gz;
-    }
-    double t1x = 0, t1y = 0, t1z = 0, ex = 0, ey = 0, ez = 0;
-    if (DL) {
-        const double nx = T.n[0], ny = T.n[1], nz = T.n[2], b = T.b;
-        const double hx = s.x - T.x0[0], hy = s.y - T.x0[1], hz = s.z - T.x0[2];
-        const double ax = s.q[0] - T.q0[0], ay = s.q[1] - T.q0[1], az = s.q[2] - T.q0[2];
-        const double mx = s.nw[0], my = s.nw[1], mz = s.nw[2];
-        const double na = nx * ax + ny * ay + nz * az;
-        const double nm = nx * mx + ny * my + nz * mz;
-        const double xa = hx * ax + hy * ay + hz * az;
-        const double xm = hx * mx + hy * my + hz * mz;
-        const double xn = hx * nx + hy * ny + hz * nz;
-        const double xx = hx * hx + hy * hy + hz * hz;
-        const double nanm = na * nm;
-        const double c1n = b * nanm - xa * nm - na * xm;
-        t1x = nx * c1n - hx * nanm;
-        t1y = ny * c1n - hy * nanm;
-        t1z = nz * c1n - hz * nanm;
-        const double c2h = b * (xa * nm + na * xm) - xa * xm;
-        const double c2n = b * xa * xm;
-        const double rmb = xx - 2.0 * b * xn;  // r^2 - b^2
-        ex = hx * c2h + nx * c2n - rmb * t1x;
-        ey = hy * c2h + ny * c2n - rmb * t1y;
-        ez = hz * c2h + nz * c2n - rmb * t1z;
-    }
-    if (SER) {
-        series_delta<0, SL, DL, COMB>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, T, A);
-        series_delta<1, SL, DL, COMB>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, T, A);
-        series_delta<2, SL, DL, COMB>(r, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p, T, A);
-        return false;
-    }
-    // e^{-t_j^2} for the three deltas.  P234 (sorted deltas in the ratio 2 : 3 : 4, the default rho):
-    // B^36, B^16, B^9 of B = e^{-(t_0/6)^2}, one exponential and seven products (relative error ~50
-    // ulp), taken in the order that keeps the fewest powers alive; otherwise three exponentials.
     if (P234) {
         const double tb = r * p.inv_delta[0] * (1.0 / 6.0);
-        const double B = exp(-tb * tb);
-        const double B4 = (B * B) * (B * B), B8 = B4 * B4;
-        accumulate_delta<2, SL, DL, COMB, LO>(r, B8 * B, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
-                                    T, A);
-        const double B16 = B8 * B8;
-        accumulate_delta<1, SL, DL, COMB, LO>(r, B16, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez, p,
-                                    T, A);
-        accumulate_delta<0, SL, DL, COMB, LO>(r, (B16 * B16) * B4, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex,
-                                    ey, ez, p, T, A);
-    } else {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double tj = r * p.inv_delta[j];
-            const double Ej = exp(-tj * tj);
-            if (j == 0)
-                accumulate_delta<0, SL, DL, COMB, LO>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                            p, T, A);
-            else if (j == 1)
-                accumulate_delta<1, SL, DL, COMB, LO>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                            p, T, A);
-            else
-                accumulate_delta<2, SL, DL, COMB, LO>(r, Ej, ir, ir3, ir5, dx, dy, dz, gx, gy, gz, dg, t1x, t1y, t1z, ex, ey, ez,
-                                            p, T, A);
-        }
-    }
-    return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
-}
-
-// A near pair: the closed-form pass, then (rarely) the series pass.  The empty asm hides that the
-// second load reads the same record, so the record is not kept in registers across the first pass.
-template <bool SL, bool DL, bool P234, bool COMB, bool LO>
-__device__ __forceinline__ void near_pair_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
-                                               const DevParams &p, Acc &A)
-{
-    if (near_pair<SL, DL, false, P234, COMB, LO>(rec64[k], T, p, A)) {
-        int kk = k;
-        asm volatile("" : "+v"(kk));
-        near_pair<SL, DL, true, P234, COMB, LO>(rec64[kk], T, p, A);
-    }
-}
-
-// Combined closed-form pass (COMB): the kernels are linear in (s1, s2, s3), so
-// sum_j w_j K(s(t_j)) = K(S) with S_k = sum_j w_j s_k(t_j): the three smoothing lengths share one kernel
-// evaluation and one set of accumulators.  Returns whether t < kSeriesT for some delta (then the
-// series pass adds those terms).
-template <bool SL, bool DL, bool P234, bool LO>
-__device__ __forceinline__ bool near_pair_comb(const SrcRec<double> &s, const Target &T, const DevParams &p, Acc &A)
-{
-    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 == 0.0) {
-        // target on a quadrature point: limit of s1(r/delta)/r is 2/(sqrt(pi) delta); the d d s2/r^3
-        // term and the whole double-layer term vanish
-        if (SL) {
-            const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
-            const double l = kTwoOverSqrtPi *
-                             (T.w[0] * p.inv_delta[0] + T.w[1] * p.inv_delta[1] + T.w[2] * p.inv_delta[2]);
-            A.sl[0][0] += gx * l;
-            A.sl[0][1] += gy * l;
-            A.sl[0][2] += gz * l;
-        }
-        return false;
-    }
-    const double ir = rsqrt(r2);
-    const double r = r2 * ir;
-    // e^{-t_j^2}: with P234 (sorted deltas in the ratio 2 : 3 : 4) B^9, B^16, B^36 of
-    // B = e^{-(t_0/6)^2}, one exponential; otherwise one per delta
-    double E0, E1, E2;
-    if (P234) {
-        const double tb = r * p.inv_delta[0] * (1.0 / 6.0);
-        const double B = exp(-tb * tb);
+        const double B = exp_nonpos(-tb * tb);
         const double B4 = (B * B) * (B * B), B8 = B4 * B4, B16 = B8 * B8;
         E2 = B8 * B;
         E1 = B16;
         E0 = (B16 * B16) * B4;
     } else {
         const double t0 = r * p.inv_delta[0], t1 = r * p.inv_delta[1], t2 = r * p.inv_delta[2];
-        E0 = exp(-t0 * t0);
-        E1 = exp(-t1 * t1);
-        E2 = exp(-t2 * t2);
+        E0 = exp_nonpos(-t0 * t0);
+        E1 = exp_nonpos(-t1 * t1);
+        E2 = exp_nonpos(-t2 * t2);
     }
-    double S1, S2, S3;
-    {
-        double a1, a2, a3;
-        smoothing3<LO>(r * p.inv_delta[2], E2, p.cutoff, a1, a2, a3);
-        S1 = T.w[2] * a1;
-        S2 = T.w[2] * a2;
-        S3 = T.w[2] * a3;
-        // the two smaller deltas: when no pair of the wavefront's batch lies within their cut-off ball
-        // (the candidates of a batch come from a few neighbouring cells, so about 40% of the batches
-        // lie beyond cutoff * delta_0) their factors are 1 exactly and the evaluation is skipped
-        const double t1 = r * p.inv_delta[1], t0 = r * p.inv_delta[0];
-        if (__ballot(t1 <= p.cutoff)) {
-            smoothing3<LO>(t1, E1, p.cutoff, a1, a2, a3);
-            S1 = __builtin_fma(T.w[1], a1, S1);
-            S2 = __builtin_fma(T.w[1], a2, S2);
-            S3 = __builtin_fma(T.w[1], a3, S3);
-        } else {
-            S1 += T.w[1];
-            S2 += T.w[1];
-            S3 += T.w[1];
-        }
-        if (__ballot(t0 <= p.cutoff)) {
-            smoothing3<LO>(t0, E0, p.cutoff, a1, a2, a3);
-            S1 = __builtin_fma(T.w[0], a1, S1);
-            S2 = __builtin_fma(T.w[0], a2, S2);
-            S3 = __builtin_fma(T.w[0], a3, S3);
-        } else {
-            S1 += T.w[0];
-            S2 += T.w[0];
-            S3 += T.w[0];
-        }
-    }
-    const double ir3 = (ir * ir) * ir;
+}
+
+// One smoothing length's share of the combined factors.  With s1 = 1 - E R, s2 = 1 - E P2 and
+// s2 - s3 = kD3 t^3 E (E = e^{-t^2}, R = erfcx(t), P2 = R + (2/sqrt(pi)) t; eqs. (s1)-(s3)) and weights
+// summing to one:  S1 = sum_j w_j s1(t_j) = 1 - a1,  S2 = 1 - a2,  S2 - S3 = kD3 ad  with
+// a1 = sum w_j E_j R_j,  a2 = sum w_j E_j P2_j,  ad = sum w_j E_j t_j^3;  beyond the cut-off the
+// factors are 1 exactly (E taken as 0).
+template <bool LO>
+__device__ __forceinline__ void smooth_acc(double t, double E, double w, double cutoff, double &a1, double &a2,
+                                           double &ad)
+{
+    // no clamp to the table's interval [0, 6.25]: beyond the cut-off E is taken as 0, and the
+    // interpolant stays finite for every t >= 0 (its variable (t - L)/(t + L) lies in [-1, 1))
+    const double R = erfcx_eval<LO>(t);
+    const double P2 = __builtin_fma(kTwoOverSqrtPi, t, R);
+    const double we = t > cutoff ? 0.0 : w * E;
+    a1 = __builtin_fma(we, R, a1);
+    a2 = __builtin_fma(we, P2, a2);
+    ad = __builtin_fma(we * t, t * t, ad);
+}
+
+// The density factors of a pair, independent of the smoothing (eqs. (Stokes_SL1), (Stokes_DL1), (Tsplit)):
+//   single layer: g = f w - c n w (c = f(x0).n0), dg = d.g;
+//   double layer: with a = q - q0, m = n w, d = y - x = b n0 - xh (xh = x - x0):
+//     t1 = n0 (b (n0.a)(n0.m) - (xh.a)(n0.m) - (n0.a)(xh.m)) - xh (n0.a)(n0.m) = n0 cn + d (n0.a)(n0.m),
+//     cn = (d.a)(n0.m) + (n0.a)(d.m) - 2 b (n0.a)(n0.m),
+//   and t2 - (r^2 - b^2) t1 = d (d.a)(d.m) - r^2 t1 (because t2 + b^2 t1 = d (d.a)(d.m)), so the
+//   split stresslet's t1 s2/r^3 + (t2 - (r^2 - b^2) t1) s3/r^5 = t1 (s2 - s3)/r^3 + d (d.a)(d.m) s3/r^5
+//   = n0 [cn (s2 - s3)/r^3] + d [(n0.a)(n0.m)(s2 - s3)/r^3 + (d.a)(d.m) s3/r^5]: the n0 part is a
+//   scalar sum per target, multiplied by n0 once at the end.
+struct PairGeo {
+    double gx, gy, gz, dg;
+    double cn, nanm, dadm;
+};
+template <bool SL, bool DL>
+__device__ __forceinline__ PairGeo pair_geo(const SrcRec<double> &s, const TgtV &T, double dx, double dy, double dz)
+{
+    PairGeo G{};
     if (SL) {
-        const double gx = s.fw[0] - T.c * s.nw[0], gy = s.fw[1] - T.c * s.nw[1], gz = s.fw[2] - T.c * s.nw[2];
-        const double dg = dx * gx + dy * gy + dz * gz;
-        const double k1 = S1 * ir, k2 = dg * S2 * ir3;
-        A.sl[0][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[0][0]));
-        A.sl[0][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[0][1]));
-        A.sl[0][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[0][2]));
+        G.gx = __builtin_fma(-T.c, s.nw[0], s.fw[0]);
+        G.gy = __builtin_fma(-T.c, s.nw[1], s.fw[1]);
+        G.gz = __builtin_fma(-T.c, s.nw[2], s.fw[2]);
+        G.dg = __builtin_fma(dz, G.gz, __builtin_fma(dy, G.gy, dx * G.gx));
     }
     if (DL) {
-        const double nx = T.n[0], ny = T.n[1], nz = T.n[2], b = T.b;
-        const double hx = s.x - T.x0[0], hy = s.y - T.x0[1], hz = s.z - T.x0[2];
         const double ax = s.q[0] - T.q0[0], ay = s.q[1] - T.q0[1], az = s.q[2] - T.q0[2];
-        const double mx = s.nw[0], my = s.nw[1], mz = s.nw[2];
-        const double na = nx * ax + ny * ay + nz * az;
-        const double nm = nx * mx + ny * my + nz * mz;
-        const double xa = hx * ax + hy * ay + hz * az;
-        const double xm = hx * mx + hy * my + hz * mz;
-        const double xn = hx * nx + hy * ny + hz * nz;
-        const double xx = hx * hx + hy * hy + hz * hz;
-        const double nanm = na * nm;
-        const double c1n = b * nanm - xa * nm - na * xm;
-        const double t1x = nx * c1n - hx * nanm;
-        const double t1y = ny * c1n - hy * nanm;
-        const double t1z = nz * c1n - hz * nanm;
-        const double c2h = b * (xa * nm + na * xm) - xa * xm;
-        const double c2n = b * xa * xm;
-        const double rmb = xx - 2.0 * b * xn;  // r^2 - b^2
-        const double ex = hx * c2h + nx * c2n - rmb * t1x;
-        const double ey = hy * c2h + ny * c2n - rmb * t1y;
-        const double ez = hz * c2h + nz * c2n - rmb * t1z;
-        const double k2 = S2 * ir3, k3 = S3 * (ir3 * (ir * ir));
-        A.dl[0][0] = __builtin_fma(ex, k3, __builtin_fma(t1x, k2, A.dl[0][0]));
-        A.dl[0][1] = __builtin_fma(ey, k3, __builtin_fma(t1y, k2, A.dl[0][1]));
-        A.dl[0][2] = __builtin_fma(ez, k3, __builtin_fma(t1z, k2, A.dl[0][2]));
+        const double na = __builtin_fma(T.n[2], az, __builtin_fma(T.n[1], ay, T.n[0] * ax));
+        const double nm = __builtin_fma(T.n[2], s.nw[2], __builtin_fma(T.n[1], s.nw[1], T.n[0] * s.nw[0]));
+        const double da = __builtin_fma(dz, az, __builtin_fma(dy, ay, dx * ax));
+        const double dm = __builtin_fma(dz, s.nw[2], __builtin_fma(dy, s.nw[1], dx * s.nw[0]));
+        G.nanm = na * nm;
+        G.cn = __builtin_fma(-2.0 * T.b, G.nanm, __builtin_fma(da, nm, na * dm));
+        G.dadm = da * dm;
     }
-    return r * p.inv_delta[2] < kSeriesT;  // inv_delta[2] is the smallest: t < kSeriesT for some delta
+    return G;
 }
 
-template <bool SL, bool DL, bool P234, bool LO>
-__device__ __forceinline__ void near_pair_comb_full(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
-                                                    const DevParams &p, Acc &A)
+// Adds K(S) for smoothing factors S1, S2, S3 = S2 - D: single layer g S1/r + d (d.g) S2/r^3
+// (eq. (Sreg)) to sl; double layer d [(n0.a)(n0.m) D/r^3 + (d.a)(d.m) S3/r^5] to dl and cn D/r^3 to
+// dn (the n0 part; the -6 is applied at the end).
+template <bool SL, bool DL>
+__device__ __forceinline__ void add_terms(double S1, double S2, double D, double ir, double dx, double dy, double dz,
+                                          const PairGeo &G, double (&sl)[3], double (&dl)[3], double &dn)
 {
-    if (near_pair_comb<SL, DL, P234, LO>(rec64[k], T, p, A)) {
-        int kk = k;
-        asm volatile("" : "+v"(kk));
-        near_pair<SL, DL, true, P234, true, LO>(rec64[kk], T, p, A);
+    const double ir2 = ir * ir, ir3 = ir2 * ir;
+    if (SL) {
+        const double k1 = S1 * ir, k2 = G.dg * S2 * ir3;
+        sl[0] = __builtin_fma(dx, k2, __builtin_fma(G.gx, k1, sl[0]));
+        sl[1] = __builtin_fma(dy, k2, __builtin_fma(G.gy, k1, sl[1]));
+        sl[2] = __builtin_fma(dz, k2, __builtin_fma(G.gz, k1, sl[2]));
+    }
+    if (DL) {
+        const double k2 = D * ir3;
+        const double kd = __builtin_fma(G.nanm, k2, (S2 - D) * (ir3 * ir2) * G.dadm);
+        dl[0] = __builtin_fma(dx, kd, dl[0]);
+        dl[1] = __builtin_fma(dy, kd, dl[1]);
+        dl[2] = __builtin_fma(dz, kd, dl[2]);
+        dn = __builtin_fma(G.cn, k2, dn);
     }
 }
 
-// A near pair of a target on the surface evaluated with the modified smoothing at one delta
-// (section 2.1): single layer with s1#, s2# (eq. (Sreg)); double layer with the stresslet's 1/r^5
-// replaced by s3#/r^5, accumulated as sum d (d.a)(d.m) s3#/r^5 like the far-field channel.  Sums go to
-// A.sl[0], A.dl[0].  SER as in near_pair.
-template <bool SL, bool DL, bool SER, bool LO>
-__device__ __forceinline__ bool near_pair_sharp(const SrcRec<double> &s, const Target &T, const DevParams &p,
-                                                Acc &A)
+// Closed-form smoothing factors of one delta for t >= kSeriesT, or the series below it (eqs.
+// (s1)-(s3)); 1 beyond the cut-off.  Returns s1, s2 and s2 - s3.
+template <bool LO>
+__device__ __forceinline__ void factors_one(double t, double cutoff, double &s1, double &s2, double &dd)
+{
+    if (t < kSeriesT) {
+        double s3;
+        series3(t, s1, s2, s3);
+        dd = s2 - s3;
+        return;
+    }
+    const double E = t > cutoff ? 0.0 : exp(-t * t);
+    const double R = erfcx_eval<LO>(fmin(t, 6.25));
+    s1 = __builtin_fma(-E, R, 1.0);
+    s2 = __builtin_fma(-E, __builtin_fma(kTwoOverSqrtPi, t, R), 1.0);
+    dd = kD3 * (E * t) * (t * t);
+}
+
+enum { kModeComb = 0, kModePerDelta = 1, kModeSharp = 2 };
+
+// The pairs the main pass leaves out (r below kSeriesT times the largest delta, r = 0 included):
+// every factor from the series or the closed form as t requires; r = 0 adds the limit of s1/r,
+// 2/(sqrt(pi) delta) (16/(3 sqrt(pi) delta) for s1#), the other terms vanish.  Rarely executed: the
+// target's own point and its closest neighbours.
+template <bool SL, bool DL, int MODE, bool LO, int NJ>
+__device__ __forceinline__ void pair_exact(const SrcRec<double> &s, const TgtV &T, const DevParams &p, AccN<NJ> &A)
 {
     const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    double gx = 0, gy = 0, gz = 0;
-    if (SL) {
-        gx = s.fw[0] - T.c * s.nw[0];
-        gy = s.fw[1] - T.c * s.nw[1];
-        gz = s.fw[2] - T.c * s.nw[2];
-    }
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    const PairGeo G = pair_geo<SL, DL>(s, T, dx, dy, dz);
     if (r2 == 0.0) {
-        // limit of s1#(r/delta)/r: 16/(3 sqrt(pi) delta); the other terms vanish
-        if (SL && !SER) {
+        if (!SL) return;
+        if (MODE == kModeSharp) {
             const double l = (8.0 / 3.0) * kTwoOverSqrtPi * p.inv_dsharp;
-            A.sl[0][0] += gx * l;
-            A.sl[0][1] += gy * l;
-            A.sl[0][2] += gz * l;
+            A.sl[0][0] += G.gx * l;
+            A.sl[0][1] += G.gy * l;
+            A.sl[0][2] += G.gz * l;
+            return;
         }
-        return false;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double l = kTwoOverSqrtPi * p.inv_delta[j] * (MODE == kModeComb ? T.w[j] : 1.0);
+            const int k = MODE == kModeComb ? 0 : j;
+            A.sl[k][0] += G.gx * l;
+            A.sl[k][1] += G.gy * l;
+            A.sl[k][2] += G.gz * l;
+        }
+        return;
     }
-    const double ir = rsqrt(r2);
-    const double r = r2 * ir;
-    const double t = r * p.inv_dsharp;
-    if (SER && !(t < kSeriesT)) return false;
-    double s1, s2, s3;
-    if (SER)
-        series3_sharp(t, s1, s2, s3);
-    else
-        smoothing3_sharp<LO>(t, p.cutoff, s1, s2, s3);
-    const double ir2 = ir * ir;
-    const double ir3 = ir2 * ir;
-    if (SL) {
-        const double dg = dx * gx + dy * gy + dz * gz;
-        const double k1 = s1 * ir, k2 = dg * s2 * ir3;
-        A.sl[0][0] = __builtin_fma(dx, k2, __builtin_fma(gx, k1, A.sl[0][0]));
-        A.sl[0][1] = __builtin_fma(dy, k2, __builtin_fma(gy, k1, A.sl[0][1]));
-        A.sl[0][2] = __builtin_fma(dz, k2, __builtin_fma(gz, k1, A.sl[0][2]));
+    const double ir = rsq64(r2), r = r2 * ir;
+    if (MODE == kModeSharp) {
+        const double t = r * p.inv_dsharp;
+        double s1, s2, s3;
+        if (t < kSeriesT)
+            series3_sharp(t, s1, s2, s3);
+        else
+            smoothing3_sharp<LO>(t, p.cutoff, s1, s2, s3);
+        // the modified double layer is d (d.a)(d.m) s3#/r^5 alone: no t1 term
+        add_terms<SL, DL>(s1, s2, s2 - s3, ir, dx, dy, dz, PairGeo{G.gx, G.gy, G.gz, G.dg, 0.0, 0.0, G.dadm},
+                          A.sl[0], A.dl[0], A.dn[0]);
+        return;
     }
-    if (DL) {
-        const double ax = s.q[0] - T.q0[0], ay = s.q[1] - T.q0[1], az = s.q[2] - T.q0[2];
-        const double da = dx * ax + dy * ay + dz * az;
-        const double dm = dx * s.nw[0] + dy * s.nw[1] + dz * s.nw[2];
-        const double co = da * dm * s3 * (ir3 * ir2);
-        A.dl[0][0] = __builtin_fma(dx, co, A.dl[0][0]);
-        A.dl[0][1] = __builtin_fma(dy, co, A.dl[0][1]);
-        A.dl[0][2] = __builtin_fma(dz, co, A.dl[0][2]);
+    double S1 = 0.0, S2 = 0.0, D = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double s1, s2, dd;
+        factors_one<LO>(r * p.inv_delta[j], p.cutoff, s1, s2, dd);
+        if (MODE == kModeComb) {
+            S1 = __builtin_fma(T.w[j], s1, S1);
+            S2 = __builtin_fma(T.w[j], s2, S2);
+            D = __builtin_fma(T.w[j], dd, D);
+        } else {
+            add_terms<SL, DL>(s1, s2, dd, ir, dx, dy, dz, G, A.sl[j], A.dl[j], A.dn[j]);
+        }
     }
-    return !SER && t < kSeriesT;
+    if (MODE == kModeComb) add_terms<SL, DL>(S1, S2, D, ir, dx, dy, dz, G, A.sl[0], A.dl[0], A.dn[0]);
 }
 
-template <bool SL, bool DL, bool LO>
-__device__ __forceinline__ void near_pair_sharp_full(const SrcRec<double> *__restrict__ rec64, int k,
-                                                     const Target &T, const DevParams &p, Acc &A)
+// One near pair in the main pass.  Lanes whose pair is closer than kSeriesT times the largest delta
+// (`rare2`: some t below kSeriesT) contribute nothing here (1/r taken as 0, r2 as 1 so that every
+// value stays finite) and go to pair_exact.
+//   kModeComb: S_k = sum_j w_j s_k(t_j) (the kernels are linear in the factors, so the three smoothing
+//     lengths share one kernel evaluation and one set of accumulators); a batch of 64 pairs skips a
+//     smoothing length when none of its pairs lies within that length's cut-off ball (a
+//     wavefront-uniform test: beyond it the factors are 1 and a1, a2, ad get nothing).
+//   kModePerDelta: three sets of accumulators (the regularized values before extrapolation).
+//   kModeSharp: the modified smoothing at one delta (section 2.1).
+template <bool SL, bool DL, int MODE, bool P234, bool LO, int NJ>
+__device__ __forceinline__ void near_pair(const SrcRec<double> &s, const TgtV &T, const DevParams &p, double rare2,
+                                          AccN<NJ> &A, bool &rare)
 {
-    if (near_pair_sharp<SL, DL, false, LO>(rec64[k], T, p, A)) {
-        int kk = k;
-        asm volatile("" : "+v"(kk));
-        near_pair_sharp<SL, DL, true, LO>(rec64[kk], T, p, A);
+    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    rare = r2 < rare2;
+    const double r2c = rare ? 1.0 : r2;
+    double ir = rsq64(r2c);
+    const double r = r2c * ir;
+    ir = rare ? 0.0 : ir;
+    if (MODE == kModeSharp) {
+        double s1, s2, s3;
+        smoothing3_sharp<LO>(r * p.inv_dsharp, p.cutoff, s1, s2, s3);
+        const PairGeo G = pair_geo<SL, DL>(s, T, dx, dy, dz);
+        add_terms<SL, DL>(s1, s2, s2 - s3, ir, dx, dy, dz, PairGeo{G.gx, G.gy, G.gz, G.dg, 0.0, 0.0, G.dadm},
+                          A.sl[0], A.dl[0], A.dn[0]);
+        return;
+    }
+    double E0, E1, E2;
+    exp3<P234>(r, p, E0, E1, E2);
+    if (MODE == kModeComb) {
+        double a1 = 0.0, a2 = 0.0, ad = 0.0;
+        smooth_acc<LO>(r * p.inv_delta[2], E2, T.w[2], p.cutoff, a1, a2, ad);
+        const double t1 = r * p.inv_delta[1], t0 = r * p.inv_delta[0];
+        if (__ballot(t1 <= p.cutoff)) smooth_acc<LO>(t1, E1, T.w[1], p.cutoff, a1, a2, ad);
+        if (__ballot(t0 <= p.cutoff)) smooth_acc<LO>(t0, E0, T.w[0], p.cutoff, a1, a2, ad);
+        const PairGeo G = pair_geo<SL, DL>(s, T, dx, dy, dz);
+        add_terms<SL, DL>(1.0 - a1, 1.0 - a2, kD3 * ad, ir, dx, dy, dz, G, A.sl[0], A.dl[0], A.dn[0]);
+    } else {
+        const PairGeo G = pair_geo<SL, DL>(s, T, dx, dy, dz);
+        const double E[3] = {E0, E1, E2};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double a1 = 0.0, a2 = 0.0, ad = 0.0;
+            smooth_acc<LO>(r * p.inv_delta[j], E[j], 1.0, p.cutoff, a1, a2, ad);
+            add_terms<SL, DL>(1.0 - a1, 1.0 - a2, kD3 * ad, ir, dx, dy, dz, G, A.sl[j], A.dl[j], A.dn[j]);
+        }
     }
 }
 
-// Extrapolation weights of eq. (extrap_eqn) for a target at signed distance b (the same for the single and
-// double layer and every component); far from the surface the smallest delta alone (w = 1, 0, 0).
-__device__ __forceinline__ void extrap_weights(double b, const DevParams &p, double w[3])
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Extrapolation weights of eq. (extrap_eqn) for the wavefront's target at signed distance b (uniform;
+// the same for the single and double layer and every component): w = e_1^T A^{-1} with rows
+// A_j = [1, rho_j I0(lambda_j), rho_j^3 I2(lambda_j)], lambda_j = b / delta_j, by Cramer's rule, the three
+// rows evaluated by lanes 0, 1, 2 side by side; far from the surface (|b| >= cutoff * max delta) the
+// smallest delta alone, w = (1, 0, 0) (every pair is beyond the cut-off there and the matrix is
+// numerically singular).
+__device__ __forceinline__ void extrap_weights_wave(double b, const DevParams &p, int lane, double w[3])
 {
     w[0] = 1.0;
     w[1] = 0.0;
     w[2] = 0.0;
     const double dmax = p.rho[2] * p.h;  // largest delta (sorted)
     if (fabs(b) < p.cutoff * dmax) {
-        double al[3], be[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double lam = b * p.inv_delta[j];
-            al[j] = p.rho[j] * I0f(lam);
-            be[j] = p.rho[j] * p.rho[j] * p.rho[j] * I2f(lam);
+        double al = 0.0, be = 0.0;
+        if (lane < 3) {
+            const double rho = lane == 0 ? p.rho[0] : (lane == 1 ? p.rho[1] : p.rho[2]);
+            const double lam = b * (lane == 0 ? p.inv_delta[0] : (lane == 1 ? p.inv_delta[1] : p.inv_delta[2]));
+            al = rho * I0f(lam);
+            be = rho * rho * rho * I2f(lam);
         }
-        const double C0 = al[1] * be[2] - al[2] * be[1];
-        const double C1 = al[2] * be[0] - al[0] * be[2];
-        const double C2 = al[0] * be[1] - al[1] * be[0];
+        const double al0 = readlane_f64(al, 0), al1 = readlane_f64(al, 1), al2 = readlane_f64(al, 2);
+        const double be0 = readlane_f64(be, 0), be1 = readlane_f64(be, 1), be2 = readlane_f64(be, 2);
+        const double C0 = al1 * be2 - al2 * be1;
+        const double C1 = al2 * be0 - al0 * be2;
+        const double C2 = al0 * be1 - al1 * be0;
         const double D = C0 + C1 + C2;
         w[0] = C0 / D;
         w[1] = C1 / D;
@@ -646,23 +588,37 @@ constexpr int depth_for() { return sizeof(TC) == 4 ? 4 : 2; }
 constexpr int kRing = 512;   // per-wave ring buffer of near pairs (power of two >= 63 + depth * 64)
 static_assert(kRing >= kWave - 1 + 4 * kWave && (kRing & (kRing - 1)) == 0, "ring buffer size");
 
-// LO: the degree-11 erfcx table of the mixed-precision path
-template <bool SL, bool DL, bool SHARP, bool P234, bool COMB, bool LO>
-__device__ __forceinline__ void eval_pair(const SrcRec<double> *__restrict__ rec64, int k, const Target &T,
-                                          const DevParams &p, Acc &A)
+// The pair of queue entry k: the main pass, then (if some lane's pair is one of the closest) the
+// exact pass on those lanes.  The record is reloaded by the exact pass rather than kept.
+template <bool SL, bool DL, int MODE, bool P234, bool LO, int NJ>
+__device__ __forceinline__ void eval_pair(const SrcRec<double> *__restrict__ rec64, int k, const TgtV &T,
+                                          const DevParams &p, double rare2, AccN<NJ> &A)
 {
-    if (SHARP)
-        near_pair_sharp_full<SL, DL, LO>(rec64, k, T, p, A);
-    else if (COMB)
-        near_pair_comb_full<SL, DL, P234, LO>(rec64, k, T, p, A);
-    else
-        near_pair_full<SL, DL, P234, false, LO>(rec64, k, T, p, A);
+    bool rare;
+    near_pair<SL, DL, MODE, P234, LO, NJ>(rec64[k], T, p, rare2, A, rare);
+    if (__ballot(rare) && rare) {
+        int kk = k;
+        asm volatile("" : "+v"(kk));
+        pair_exact<SL, DL, MODE, LO, NJ>(rec64[kk], T, p, A);
+    }
 }
 
-// COMB (only when no per-delta outputs are asked for): the weights are known before the pair loop and
-// each pair adds K(S), S_k = sum_j w_j s_k(t_j), into one set of accumulators instead of three.
-template <typename TC, bool SL, bool DL, bool SHARP, bool P234, bool COMB>
-__global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
+// Pins a value to a vector register when PIN (see TgtV).  The double-precision path runs faster with
+// its target data left to the compiler (scalar registers; near field at the 42k-source ellipsoid
+// 2.47 -> 1.99 ms), the mixed path with them in vector registers (1.81 -> 1.76 ms).  The candidate
+// test's coordinates and radius are always pinned: in single precision every operand of the test is
+// then a vector register.
+template <bool PIN, typename V>
+__device__ __forceinline__ V to_vgpr(V v)
+{
+    if (PIN) asm volatile("" : "+v"(v));
+    return v;
+}
+
+// MODE kModeComb: only the extrapolated values (weights known before the pair loop); kModePerDelta:
+// also the per-delta values; kModeSharp: the targets on the surface under the modified smoothing.
+template <typename TC, bool SL, bool DL, int MODE, bool P234>
+__global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<double> *__restrict__ rec64,
                                                                const Pos4<TC> *__restrict__ pos,
                                                                const int *__restrict__ cell_start, CellGrid grid,
                                                                EvalArgs a, DevParams p, TC rc2, TC rc2s,
@@ -671,76 +627,118 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
 {
     // single-precision candidate test = the mixed-precision path: the degree-11 erfcx table
     constexpr bool kLo = std::is_same<TC, float>::value;
+    constexpr bool SHARP = MODE == kModeSharp;
+    constexpr int NJ = MODE == kModePerDelta ? 3 : 1;
     __shared__ int queue_all[kBlock / kWave][kRing];
-    // readfirstlane: tells the compiler the wave index (hence the target) is wavefront-uniform, so the
-    // target's data live in scalar registers
+    // readfirstlane: the wave index (hence the target) is wavefront-uniform
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int lane = (int)threadIdx.x % kWave;
     int *queue = queue_all[wave];
     const int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
     if (t >= a.m) return;  // wavefront-uniform exit
 
-    Target T;
+    double ty[3], tn[3], tq0[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        T.y[i] = a.y[3 * t + i];
-        T.x0[i] = a.x0[3 * t + i];
-        T.n[i] = a.n0[3 * t + i];
-        T.q0[i] = DL ? a.q0[3 * t + i] : 0.0;
+        ty[i] = a.y[3 * t + i];
+        tn[i] = a.n0[3 * t + i];
+        tq0[i] = DL ? a.q0[3 * t + i] : 0.0;
     }
-    T.b = a.b[t];
-    // a target on the surface with the modified smoothing selected: one delta, no extrapolation
-    // (wavefront-uniform: one target per wavefront)
-    // SHARP instances take exactly these targets, the others every other target, so that each
-    // instance is compiled for one path (one register budget)
-    const bool sharp = p.sharp && T.b == 0.0;
-    if (sharp != SHARP) return;  // wavefront-uniform exit
-    T.c = SL ? a.f0[3 * t] * T.n[0] + a.f0[3 * t + 1] * T.n[1] + a.f0[3 * t + 2] * T.n[2] : 0.0;
-    if (COMB) extrap_weights(T.b, p, T.w);
-    const TC tyx = (TC)(T.y[0] - a.org[0]), tyy = (TC)(T.y[1] - a.org[1]), tyz = (TC)(T.y[2] - a.org[2]);
+    const double tb = a.b[t];
+    // a target on the surface with the modified smoothing selected: one delta, no extrapolation; the
+    // SHARP instance takes exactly these targets, the others every other target (wavefront-uniform)
+    const bool sharp = p.sharp && tb == 0.0;
+    if (sharp != SHARP) return;
+    const double tc = SL ? a.f0[3 * t] * tn[0] + a.f0[3 * t + 1] * tn[1] + a.f0[3 * t + 2] * tn[2] : 0.0;
+    double w[3] = {1.0, 0.0, 0.0};
+    if (MODE == kModeComb) extrap_weights_wave(tb, p, lane, w);
+
+    TgtV T;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T.y[i] = to_vgpr<kLo>(ty[i]);
+        T.n[i] = to_vgpr<kLo>(tn[i]);
+        T.q0[i] = to_vgpr<kLo>(tq0[i]);
+        T.w[i] = to_vgpr<kLo>(w[i]);
+    }
+    T.b = to_vgpr<kLo>(tb);
+    T.c = to_vgpr<kLo>(tc);
+    const TC tyx = to_vgpr<true>((TC)(ty[0] - a.org[0])), tyy = to_vgpr<true>((TC)(ty[1] - a.org[1])),
+             tyz = to_vgpr<true>((TC)(ty[2] - a.org[2]));
+    const TC rcv = to_vgpr<true>(SHARP ? rc2s : rc2);
+    // pairs closer than kSeriesT times the largest delta (the sharp delta for SHARP) go to pair_exact
+    const double rare2 = SHARP ? (kSeriesT / p.inv_dsharp) * (kSeriesT / p.inv_dsharp)
+                               : (kSeriesT / p.inv_delta[2]) * (kSeriesT / p.inv_delta[2]);
     // the far rule of the extrapolation (w = (1, 0, 0)) asserts that no source is within
     // cutoff * max delta: checked against the candidates (wavefront-uniform)
-    const bool farrule = !SHARP && fabs(T.b) >= p.cutoff * p.rho[2] * p.h;
+    const bool farrule = !SHARP && fabs(tb) >= p.cutoff * p.rho[2] * p.h;
     const TC rflag2 = (TC)(p.rflag * p.rflag);
     bool bad = false;
 
-    int ci[3];
+    // cells within the reach (near radius plus the rounding margin) of the target, per axis; in the
+    // xy-plane a column of cells whose box lies farther than the reach is skipped
+    const double R = SHARP ? p.reach_sharp : p.reach;
+    int lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double u = floor((T.y[d] - grid.lo[d]) * grid.inv_side);
-        u = fmin(fmax(u, -2.0), (double)grid.g[d] + 1.0);
-        ci[d] = (int)u;
+        const double l = floor((ty[d] - R - grid.lo[d]) * grid.inv_side);
+        const double u = floor((ty[d] + R - grid.lo[d]) * grid.inv_side);
+        lo[d] = (int)fmax(l, 0.0);
+        hi[d] = (int)fmin(u, (double)grid.g[d] - 1.0);
     }
 
-    Acc A;
+    AccN<NJ> A;
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < NJ; ++j) {
+        A.dn[j] = 0.0;
 #pragma unroll
         for (int i = 0; i < 3; ++i) A.sl[j][i] = A.dl[j][i] = 0.0;
+    }
 
     // Candidates are loaded kDepth steps of 64 at a time, so that kDepth loads are in flight per
-    // wavefront instead of one (the scan is otherwise a chain of dependent load latencies); the near
-    // ones go to a ring buffer in LDS (kRing >= 63 + kDepth * 64 entries) and every full 64 are evaluated.
+    // wavefront; the near ones go to a ring buffer in LDS (kRing >= 63 + kDepth * 64 entries) and every
+    // full 64 are evaluated.  The columns of the block are set up in parallel, one per lane (up to 64
+    // per pass): a column whose xy-box lies farther than the reach is dropped, the others load their
+    // record range [cs, ce); the wavefront then scans the live columns in order.
     constexpr int kDepth = depth_for<TC>();
     int head = 0, cnt = 0;  // ring buffer start and length (wavefront-uniform)
-    const int z0 = max(ci[2] - 1, 0), z1 = min(ci[2] + 1, grid.g[2] - 1);
-    for (int ix = max(ci[0] - 1, 0); ix <= min(ci[0] + 1, grid.g[0] - 1); ++ix) {
-        for (int iy = max(ci[1] - 1, 0); iy <= min(ci[1] + 1, grid.g[1] - 1); ++iy) {
-            if (z0 > z1) continue;
-            const int cb = (ix * grid.g[1] + iy) * grid.g[2];
-            const int s0 = cell_start[cb + z0], s1 = cell_start[cb + z1 + 1];
+    const double R2 = R * R;
+    const int nyc = hi[1] - lo[1] + 1;
+    const int ncol = (hi[0] >= lo[0] && hi[1] >= lo[1] && hi[2] >= lo[2]) ? (hi[0] - lo[0] + 1) * nyc : 0;
+    for (int cb0 = 0; cb0 < ncol; cb0 += kWave) {
+        int cs = 0, ce = 0;
+        {
+            const int j = cb0 + lane;
+            if (j < ncol) {
+                const int jx = j / nyc;
+                const int ix = lo[0] + jx, iy = lo[1] + (j - jx * nyc);
+                const double cx = grid.lo[0] + ix * grid.side, cy = grid.lo[1] + iy * grid.side;
+                const double ex = fmax(0.0, fmax(cx - ty[0], ty[0] - (cx + grid.side)));
+                const double ey = fmax(0.0, fmax(cy - ty[1], ty[1] - (cy + grid.side)));
+                if (ex * ex + ey * ey <= R2) {
+                    const int cb = (ix * grid.g[1] + iy) * grid.g[2];
+                    cs = cell_start[cb + lo[2]];
+                    ce = cell_start[cb + hi[2] + 1];
+                }
+            }
+        }
+        for (uint64_t live = __ballot(ce > cs); live; live &= live - 1) {
+            const int jl = (int)__builtin_ctzll(live);
+            const int s0 = __builtin_amdgcn_readlane(cs, jl), s1 = __builtin_amdgcn_readlane(ce, jl);
             for (int base = s0; base < s1; base += kDepth * kWave) {
+                // only the steps of 64 that hold candidates (a wavefront-uniform count); the index is
+                // clamped to the column so that every lane loads (no divergent branch)
+                const int nsl = min(kDepth, (s1 - base + kWave - 1) / kWave);
                 Pos4<TC> q[kDepth];
 #pragma unroll
-                for (int u = 0; u < kDepth; ++u) {
-                    const int k = base + u * kWave + lane;
-                    if (k < s1) q[u] = pos[k];
-                }
+                for (int u = 0; u < kDepth; ++u)
+                    if (u < nsl) q[u] = pos[min(base + u * kWave + lane, s1 - 1)];
 #pragma unroll
                 for (int u = 0; u < kDepth; ++u) {
+                    if (u >= nsl) break;
                     const int k = base + u * kWave + lane;
                     const TC r2c = pair_r2(tyx, tyy, tyz, q[u].x, q[u].y, q[u].z);
-                    const bool nr = k < s1 && r2c <= (SHARP ? rc2s : rc2);
+                    const bool nr = k < s1 && r2c <= rcv;
                     if (farrule) bad = bad || (nr && r2c < rflag2);
                     const uint64_t m = __ballot(nr);
                     if (nr) {
@@ -756,57 +754,58 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
                     wave_lds_sync();
                     head = (head + kWave) & (kRing - 1);
                     cnt -= kWave;
-                    eval_pair<SL, DL, SHARP, P234, COMB, kLo>(rec64, k2, T, p, A);
+                    eval_pair<SL, DL, MODE, P234, kLo, NJ>(rec64, k2, T, p, rare2, A);
                 }
             }
         }
     }
     wave_lds_sync();
-    if (lane < cnt) eval_pair<SL, DL, SHARP, P234, COMB, kLo>(rec64, queue[(head + lane) & (kRing - 1)], T, p, A);
+    if (lane < cnt) eval_pair<SL, DL, MODE, P234, kLo, NJ>(rec64, queue[(head + lane) & (kRing - 1)], T, p, rare2, A);
     if (farrule && __ballot(bad) && lane == 0) {
         atomicOr(&flag->bits, kFlagFarRule);
         atomicMin(&flag->first, (unsigned long long)t);
     }
 
-    constexpr int NJ = COMB ? 1 : 3;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
+    for (int j = 0; j < NJ; ++j) {
+        if (DL) A.dn[j] = wave_sum(A.dn[j]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             if (SL) A.sl[j][i] = wave_sum(A.sl[j][i]);
-            if (DL) A.dl[j][i] = wave_sum(A.dl[j][i]);
+            if (DL) A.dl[j][i] = __builtin_fma(tn[i], A.dn[j], wave_sum(A.dl[j][i]));
         }
+    }
 
-    const double b = T.b;
-    const double chi = b < 0.0 ? 1.0 : (b > 0.0 ? 0.0 : 0.5);
+    const double chi = tb < 0.0 ? 1.0 : (tb > 0.0 ? 0.0 : 0.5);
     const double inv8pi = 1.0 / (8.0 * kPi);
 
-    if (COMB) {
+    if (MODE != kModePerDelta) {
+        // combined (or single-delta) sums: u = (far + sum_j w_j near_j) / (8 pi)
         if (lane < 3) {
             const int i = lane;
             if (SL) {
                 double far = 0.0;
                 for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + i) * (size_t)a.m + t];
                 a.u[3 * t + i] = (far + pick3(A.sl[0], i)) * inv8pi;
+                if (a.u_delta)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * p.ord[j] + i] = a.u[3 * t + i];
             }
             if (DL) {
                 double far = 0.0;
                 for (int sp = 0; sp < nparts; ++sp) far += part[((size_t)sp * 6 + 3 + i) * (size_t)a.m + t];
-                a.v[3 * t + i] = -6.0 * (far + pick3(A.dl[0], i)) * inv8pi + chi * pick3(T.q0, i);
+                const double vv = -6.0 * (far + pick3(A.dl[0], i)) * inv8pi;
+                a.v[3 * t + i] = vv + chi * pick3(tq0, i);
+                if (a.v_delta)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * p.ord[j] + i] = vv;
             }
         }
         return;
     }
 
-    double w0 = 1.0, w1 = 0.0, w2 = 0.0;
-    if (!SHARP) {
-        double w[3];
-        extrap_weights(b, p, w);
-        w0 = w[0];
-        w1 = w[1];
-        w2 = w[2];
-    }
-
+    double wx[3];
+    extrap_weights_wave(tb, p, lane, wx);
     if (lane < 3) {
         const int i = lane;
         if (SL) {
@@ -815,10 +814,10 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
             double uj[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) uj[j] = (far + pick3(A.sl[j], i)) * inv8pi;
-            a.u[3 * t + i] = w0 * uj[0] + w1 * uj[1] + w2 * uj[2];
+            a.u[3 * t + i] = wx[0] * uj[0] + wx[1] * uj[1] + wx[2] * uj[2];
             if (a.u_delta)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * p.ord[j] + i] = SHARP ? uj[0] : uj[j];
+                for (int j = 0; j < 3; ++j) a.u_delta[9 * t + 3 * p.ord[j] + i] = uj[j];
         }
         if (DL) {
             double far = 0.0;
@@ -826,10 +825,10 @@ __global__ __launch_bounds__(kBlock, P234 ? 4 : 1) void near_finalize_kernel(con
             double vj[3];
 #pragma unroll
             for (int j = 0; j < 3; ++j) vj[j] = -6.0 * (far + pick3(A.dl[j], i)) * inv8pi;
-            a.v[3 * t + i] = w0 * vj[0] + w1 * vj[1] + w2 * vj[2] + chi * pick3(T.q0, i);
+            a.v[3 * t + i] = wx[0] * vj[0] + wx[1] * vj[1] + wx[2] * vj[2] + chi * pick3(tq0, i);
             if (a.v_delta)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * p.ord[j] + i] = SHARP ? vj[0] : vj[j];
+                for (int j = 0; j < 3; ++j) a.v_delta[9 * t + 3 * p.ord[j] + i] = vj[j];
         }
     }
 }
@@ -845,20 +844,20 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
     const TC rc2s = (TC)(p.rsharp * p.rsharp);  // near radius of the surface targets of the SHARP instance
     const dim3 grid((unsigned)blocks), block(kBlock);
     if (p.pow234 && comb)
-        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, true>), grid, block, 0, s, rec64, pos,
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModeComb, true>), grid, block, 0, s, rec64, pos,
                            cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     else if (p.pow234)
-        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, true, false>), grid, block, 0, s, rec64, pos,
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModePerDelta, true>), grid, block, 0, s, rec64, pos,
                            cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     else if (comb)
-        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, true>), grid, block, 0, s, rec64, pos,
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModeComb, false>), grid, block, 0, s, rec64, pos,
                            cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     else
-        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, false, false, false>), grid, block, 0, s, rec64, pos,
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModePerDelta, false>), grid, block, 0, s, rec64, pos,
                            cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !p.sharp) return e;
-    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, true, false, false>), grid, block, 0, s, rec64, pos,
+    hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModeSharp, false>), grid, block, 0, s, rec64, pos,
                        cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     return hipGetLastError();
 }
@@ -874,7 +873,6 @@ hipError_t dispatch(int layers, const SrcRec<double> *rec64, const Pos4<TC> *pos
         return launch_t<TC, true, false>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, flag, s);
     return launch_t<TC, false, true>(rec64, pos, cell_start, g, a, p, rc2, part, nparts, flag, s);
 }
-
 // Far field added to outputs that already hold the near sums, the extrapolation and the jump term
 // (the near kernel run with no far partial sums, concurrently with the far-field kernel).  The
 // extrapolation weights w = e_1^T A^{-1} of eq. (extrap_eqn) satisfy w A = e_1^T and the first column

@@ -6,6 +6,7 @@ degree-11 table.  A wrong coefficient, degree or variable map fails by many orde
 import math
 import os
 import re
+from fractions import Fraction
 
 import mpmath
 import pytest
@@ -30,14 +31,21 @@ def tables():
     return out
 
 
+def _fma(a, b, c):
+    """a * b + c with one rounding (exact rational arithmetic, then one conversion to float)."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
 def erfc_from_table(T, t):
-    # the kernels' steps: inv = 1/(t + L), x = A (t - L) inv + B, Horner, erfcx = L inv P(x)
+    # the kernels' steps: inv = 1/(t + L), x = (A + B) - 2 A L inv, Horner on the coefficients times L,
+    # erfcx = inv P_L(x) (_fma keeps the kernels' single roundings)
     inv = 1.0 / (t + T["L"])
-    x = T["A"] * ((t - T["L"]) * inv) + T["B"]
-    p = T["c"][-1]
-    for c in reversed(T["c"][:-1]):
-        p = p * x + c
-    return math.exp(-t * t) * (T["L"] * inv * p)
+    x = _fma(-2.0 * T["A"] * T["L"], inv, T["A"] + T["B"])
+    cl = [T["L"] * c for c in T["c"]]
+    p = cl[-1]
+    for c in reversed(cl[:-1]):
+        p = _fma(p, x, c)
+    return math.exp(-t * t) * (inv * p)
 
 
 @pytest.mark.parametrize("name,degree,bound", [("Fp64", 16, 1e-15), ("Mixed", 11, 2e-11)])

@@ -216,10 +216,13 @@ def test_concurrent_phases_equal_serial(P, small, precision, far):
     # stream concurrently with the far field, and the far sum is added afterwards; with profiling on,
     # the phases run one after the other and the near kernel adds the far sum itself.  The two differ
     # only in rounding: (far + near) / (8 pi) against near / (8 pi) + far / (8 pi).  Three
-    # evaluations are enqueued back to back on a non-default stream, each with its densities scaled
-    # by 2^k (exact in every precision) and its outputs copied right after on the same stream: a copy
-    # taken before the near kernel or the far addition finished would differ from 2^k times the
-    # serial result.
+    # evaluations with densities scaled by 2^k are enqueued back to back on a non-default stream, each
+    # with its outputs copied right after on the same stream, and each is compared with a serial
+    # evaluation of the same densities: a copy taken before the near kernel or the far addition
+    # finished, or a kernel reading the previous call's records, would differ at the 1e-1 level.  (The
+    # serial results are not assumed to scale exactly with 2^k: in single precision, products with
+    # the tiny quadrature weights near the partition-of-unity cut-off underflow, and gradual
+    # underflow is not homogeneous.)
     import torch
 
     cfg, (u_or, v_or, _, _) = small
@@ -229,17 +232,20 @@ def test_concurrent_phases_equal_serial(P, small, precision, far):
     ev.set_surface(to_dev(s.x), to_dev(s.normal), to_dev(s.w))
     f, q, f0, q0 = (to_dev(cfg[k]) for k in ("f", "q", "f0", "q0"))
     y, x0, n0, b = (to_dev(a) for a in (t.y, t.x0, t.n0, t.b))
-    ev.set_density(P.SR_SL, f)
-    ev.set_density(P.SR_DL, q)
-    torch.cuda.synchronize()
-    P.sr_set_profiling(ev.ctx, True)
-    us, vs = ev.eval(3, y, x0, n0, b, f0, q0)
-    torch.cuda.synchronize()
-    P.sr_set_profiling(ev.ctx, False)
-    P.sr_get_profile(ev.ctx)
-    us, vs = us.cpu().numpy(), vs.cpu().numpy()
     tol = TOL[precision] if far == "direct" else 1e-3  # the treecode's own error against the direct oracle
-    assert rel_err(us, u_or) <= tol and rel_err(vs, v_or) <= tol
+    serial = []
+    for k in range(3):
+        c = float(2**k)
+        ev.set_density(P.SR_SL, f * c)
+        ev.set_density(P.SR_DL, q * c)
+        torch.cuda.synchronize()
+        P.sr_set_profiling(ev.ctx, True)
+        us, vs = ev.eval(3, y, x0, n0, b, f0 * c, q0 * c)
+        torch.cuda.synchronize()
+        P.sr_set_profiling(ev.ctx, False)
+        P.sr_get_profile(ev.ctx)
+        serial.append((us.cpu().numpy(), vs.cpu().numpy()))
+        assert rel_err(serial[-1][0], c * u_or) <= tol and rel_err(serial[-1][1], c * v_or) <= tol
 
     st = torch.cuda.Stream()
     snaps, keep = [], []
@@ -255,7 +261,7 @@ def test_concurrent_phases_equal_serial(P, small, precision, far):
     torch.cuda.synchronize()
     ev.close()
     for k, (uk, vk) in enumerate(snaps):
-        e1 = rel_err(uk.cpu().numpy(), 2**k * us)
-        e2 = rel_err(vk.cpu().numpy(), 2**k * vs)
+        e1 = rel_err(uk.cpu().numpy(), serial[k][0])
+        e2 = rel_err(vk.cpu().numpy(), serial[k][1])
         print(f"concurrent {far} prec={precision} k={k}: SL {e1:.2e} DL {e2:.2e}", flush=True)
         assert e1 <= 1e-13 and e2 <= 1e-13
