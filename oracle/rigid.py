@@ -14,8 +14,11 @@ Appl. Math. 47 (1987)); the paper's double-layer evaluation supplies every integ
 
 -1/2 q + DL_PV is the exterior limit of the double layer (its jump is q, eq. (Stokes_DL1)); the
 completion removes the rigid-motion null space.  q(x0): tensor Lagrange interpolation on the grid of a
-quadrature family i on the sheet sign(n_i(x0)): the first of widths 4, 3, 2 points per axis, and for
-each width the families in decreasing |n_i(x0)| order, whose stencil points all exist.  GMRES: the textbook algorithm with modified Gram-Schmidt and Givens rotations.
+quadrature family i on the sheet sign(n_i(x0)): the first of widths 6, 5, 4, 3, 2 points per axis
+(6 x 6 points: O(h^6) where the full stencil exists), and for each width the families in decreasing
+|n_i(x0)| order, whose stencil points all exist.  The paper does not say how q(x0) is obtained when
+x0 is not a quadrature point; this is the reading taken, and the same routine prolongs a density from
+the quadrature of spacing h to that of spacing h/2.  GMRES: the textbook algorithm with modified Gram-Schmidt and Givens rotations.
 """
 from __future__ import annotations
 
@@ -62,18 +65,18 @@ class Sphere:
         return self.c + self.a * n0, n0, r - self.a
 
     def stencils(self, x0):
-        """Indices (K,16) and weights (K,16) of the interpolation stencils at surface points x0:
-        width 4 (cubic), else 3, else 2 points per axis, each tried over the families in decreasing
+        """Indices (K,36) and weights (K,36) of the interpolation stencils at surface points x0:
+        width 6 (quintic), else 5, 4, 3, 2 points per axis, each tried over the families in decreasing
         |n_i| order; unused slots have weight 0 and index 0."""
         loc = np.asarray(x0, float) - self.c
         h = self.h
         K = len(loc)
-        idx = np.zeros((K, 16), dtype=np.int64)
-        wts = np.zeros((K, 16))
+        idx = np.zeros((K, 36), dtype=np.int64)
+        wts = np.zeros((K, 36))
         for t in range(K):
             order = np.argsort(-np.abs(loc[t]), kind="stable")
             done = False
-            for wdt in (4, 3, 2):
+            for wdt in (6, 5, 4, 3, 2):
                 for i in order:
                     j, k = [d for d in range(3) if d != i]
                     sg = 1 if loc[t, i] > 0 else -1

@@ -3,7 +3,8 @@
 - completion closed forms on one unit sphere: A U = (1/8 pi) (sum w) (U + n (n.U)) exactly for a
   constant density (the subtracted double layer of a constant is chi q = q/2 on the surface), and
   A (Omega x d) ~ (1/3) Omega x d (rotlet of L = (8 pi / 3) Omega);
-- interpolation stencil: the cubic tensor stencil's error at points off the grid falls like h^4;
+- interpolation stencil: the 6 x 6 tensor stencil's error at points off the grid falls like h^6, and
+  it reproduces polynomials of degree 5 in each grid coordinate exactly;
 - single translating / rotating sphere: the solved density's exterior flow equals Stokes' solution;
 - GMRES: matches a dense solve on a small nonsymmetric system.
 """
@@ -42,7 +43,7 @@ def test_completion_of_rotation():
     assert err <= 2e-3
 
 
-def test_stencil_error_is_fourth_order():
+def test_stencil_error_is_sixth_order():
     errs = []
     rng = np.random.default_rng(7)
     d = rng.standard_normal((40, 3))
@@ -52,15 +53,50 @@ def test_stencil_error_is_fourth_order():
         return np.stack([np.sin(1.3 * x[:, 0] + 0.4 * x[:, 1]), np.cos(x[:, 2] - 0.7 * x[:, 0]),
                          np.exp(0.5 * x[:, 1]) * x[:, 2]], axis=1)
 
-    for h in (1 / 8, 1 / 16):
+    for h in (1 / 16, 1 / 32, 1 / 64):
         s = workload.sphere_quadrature(h)
         sp = Sphere(s, np.zeros(3), 1.0, h)
         idx, wts = sp.stencils(d)
+        # near the corners of the families' sheets a coarse grid has no 6 x 6 stencil (narrower ones
+        # are taken there); from h = 1/32 on every point has one
+        assert (np.count_nonzero(wts, axis=1) == 36).all() or h == 1 / 16
         q = field(s.x)
         est = np.einsum("ks,ksc->kc", wts, q[idx])
         errs.append(np.abs(est - field(d)).max())
-    print("stencil errors", errs)
-    assert errs[1] <= errs[0] / 10 and errs[1] <= 1e-4
+    print("stencil errors", errs, "ratios", errs[0] / errs[1], errs[1] / errs[2])
+    # h^6: a factor 64 per halving (asymptotically); h^4 would give 16
+    assert errs[1] / errs[2] >= 40 and errs[2] <= 1e-8
+
+
+def test_stencil_reproduces_quintic_polynomials():
+    """On a sheet of family i the grid coordinates are (x_j, x_k); a polynomial of degree <= 5 in
+    each of them is interpolated exactly by the 6 x 6 tensor stencil (to rounding)."""
+    h = 1 / 16
+    s = workload.sphere_quadrature(h)
+    sp = Sphere(s, np.zeros(3), 1.0, h)
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal((200, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    idx, wts = sp.stencils(d)
+    full = np.count_nonzero(wts, axis=1) == 36
+    assert full.mean() > 0.9
+    # the family of each stencil: the axis whose coordinate is not a grid coordinate of all its points
+    C = rng.standard_normal((6, 6))
+
+    def poly(a, b):
+        return sum(C[i, j] * a ** i * b ** j for i in range(6) for j in range(6))
+
+    bad = 0
+    for t in np.nonzero(full)[0]:
+        pts = s.x[idx[t]]
+        fam = [i for i in range(3) if np.allclose(np.round(pts[:, [j for j in range(3) if j != i]] / h),
+                                                    pts[:, [j for j in range(3) if j != i]] / h, atol=1e-9)]
+        i = fam[0]
+        j, k = [e for e in range(3) if e != i]
+        got = wts[t] @ poly(pts[:, j], pts[:, k])
+        ex = poly(d[t, j], d[t, k])
+        bad += abs(got - ex) > 1e-10 * max(1.0, abs(ex))
+    assert bad == 0
 
 
 @pytest.mark.parametrize("kind", ["translate", "rotate"])
