@@ -210,8 +210,9 @@ sr_status sr_tree_work(sr_ctx *c, int64_t m, const double *y, int64_t *proxy_pai
  *   F_m = sum_p q_p w_p,  L_m = sum_p (x_p - c_m) x q_p w_p   (sums over sphere m),
  *
  * where DL_m of a sphere's own points is the on-surface value (chi = 1/2) and of other points the
- * nearly singular exterior value with q(x0) interpolated on the quadrature grid (cubic, else
- * quadratic, else linear tensor Lagrange on one coordinate family).  A q = U_b + Omega_b x (x - c_b)
+ * nearly singular exterior value with q(x0) interpolated on the quadrature grid (tensor Lagrange
+ * on one coordinate family, 6 x 6 points (O(h^6)), else 5, 4, 3, 2 per axis where the sheet has no
+ * wider stencil).  A q = U_b + Omega_b x (x - c_b)
  * is the rigid-motion problem.  Unknowns and targets: the quadrature points of all spheres, sphere
  * by sphere, (ntot,3).  The quadrature must be the grid-line quadrature of paper section 2.2 with
  * the parameters' h, generated in each sphere's frame centred at its centre. */
@@ -267,8 +268,8 @@ const char *sr_rigid_last_error(void);
 
 /* Coarse-to-fine interpolation of densities on spheres (the warm start computes the density on a
  * coarse quadrature and the solve needs it on a fine one).  Each fine point's value is the tensor
- * Lagrange interpolant on the coarse grid of one coordinate family (cubic, else quadratic, else
- * linear; the family with the largest |n_i| whose stencil exists), as for q(x0) above.
+ * Lagrange interpolant on the coarse grid of one coordinate family (6 x 6 points, else narrower;
+ * the family with the largest |n_i| whose stencil exists), as for q(x0) above.
  * centers (nsph,3), radii, counts_c, counts_f on the HOST; xc, nc (coarse points and normals,
  * NC = sum counts_c) and xf (fine points, NF = sum counts_f) on the device, sphere by sphere, each
  * sphere's coarse set being the grid-line quadrature with spacing hc in its own frame.  Synchronizes
@@ -287,7 +288,9 @@ sr_status sr_prolong_destroy(sr_prolong *p);
  *   gt = (ln g - g_mid) / g_half;  h1 = tanh(W1 gt + b1);  h2 = tanh(W2 h1 + b2);  h3 = tanh(W3 h2 + b3)
  *   a4 = W4 h3 + b4 (12 width);  z_w = sum_k a4[12 w + k] m_k;  o = Wh z;  q = s o (s per output)
  * Matrix products run on BF16 matrix cores with FP32 accumulation; each FP32 operand is split into
- * BF16 hi + lo and `passes` = 3 (default) sums hi*hi + hi*lo + lo*hi, passes = 1 uses hi*hi only.
+ * BF16 hi + lo + lo2 (the whole FP32 significand); `passes` = 3 (default) sums hi*hi + hi*lo + lo*hi
+ * (about 16 significant bits), passes = 6 adds lo*lo + hi*lo2 + lo2*hi (about 24 bits, twice the
+ * matrix-core work), passes = 1 uses hi*hi only.
  * Training: loss = mean over batch and outputs of (o - y/s)^2; Adam (beta 0.9, 0.999, eps 1e-8)
  * on FP32 master weights.
  * Parameters: one FP32 vector, blocks in the order W1 (width,1), b1, W2 (width,width), b2, W3, b3,
@@ -302,7 +305,7 @@ int64_t sr_mlp_num_params(int width, int64_t nout);
 /* width: multiple of 32 in 32..4096; max_batch 1..4096. */
 sr_status sr_mlp_create(sr_mlp **out, int device, int width, int64_t nout, int max_batch);
 sr_status sr_mlp_destroy(sr_mlp *net);
-/* passes 1 or 3; input normalization g_mid, g_half > 0 of ln g (defaults: ln 0.02 .. ln 0.2 -> -1 .. 1,
+/* passes 1, 3 or 6; input normalization g_mid, g_half > 0 of ln g (defaults: ln 0.02 .. ln 0.2 -> -1 .. 1,
  * g_mid = -2.7607, g_half = 1.1513).  The gap must be > 0. */
 sr_status sr_mlp_set_options(sr_mlp *net, int passes, double g_mid, double g_half);
 /* HOST parameter vector in, out.  Setting resets the Adam moments and step count, and the output
@@ -335,7 +338,7 @@ enum { SR_MLP_PHASE_FORWARD = 0, SR_MLP_PHASE_BACKWARD = 1, SR_MLP_PHASE_ADAM = 
 sr_status sr_mlp_set_profiling(sr_mlp *net, int on);
 sr_status sr_mlp_get_profile(sr_mlp *net, double *ms, int64_t *steps);
 /* The matrix-product kernel alone, for testing: C (m,n) = A (m,k) B^T with B (n,k), FP32 row-major
- * device arrays, through BF16 hi/lo operands and `passes` products.  Synchronizes `stream`. */
+ * device arrays, through the BF16 pieces of the operands and `passes` products.  Synchronizes `stream`. */
 sr_status sr_mlp_gemm_test(int device, int passes, int m, int n, int k, const float *a, const float *b, float *c,
                            void *stream);
 /* Message describing the last sr_mlp_* failure on this thread. */

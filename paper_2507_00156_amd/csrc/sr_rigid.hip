@@ -11,9 +11,10 @@
 //            removes the rigid-motion null space of -1/2 I + DL; Power & Miranda 1987).
 //
 // q(x0): tensor Lagrange interpolation on the grid of one quadrature family (paper section 2.2): the
-// first of widths 4, 3, 2 points per axis and, per width, the families in decreasing |n_i(x0)| order
-// whose stencil points all exist, on the sheet sign(n_i(x0)).  Stencils depend on the geometry only
-// and are built on the host once.
+// first of widths 6, 5, 4, 3, 2 points per axis (6 x 6: O(h^6)) and, per width, the families in
+// decreasing |n_i(x0)| order whose stencil points all exist, on the sheet sign(n_i(x0)).  Stencils
+// depend on the geometry only and are built on the host once; kStencil slots per target, unused ones
+// with weight 0.
 //
 // GMRES(restart): Arnoldi with classical Gram-Schmidt applied twice (one block dot product and one
 // block update per pass), Givens rotations on the host, residual estimate from the rotated right-hand
@@ -85,6 +86,9 @@ struct Buf {
 
 // ---------------------------------------------------------------- kernels
 
+constexpr int kStencilWidth = 6;
+constexpr int kStencil = kStencilWidth * kStencilWidth;
+
 // q0 of sphere m at every target: the density itself for the sphere's own points (targets
 // [own0, own1), whose density sits at the same index), the interpolated density at the closest point
 // otherwise (stencil indices relative to the sphere's first point soff).
@@ -98,9 +102,9 @@ __global__ void gather_q0_kernel(const double *__restrict__ q, int64_t nt, int64
     if (t >= own0 && t < own1) {
         for (int c = 0; c < 3; ++c) v[c] = q[3 * t + c];
     } else {
-        for (int s = 0; s < 16; ++s) {
-            const double wv = wts[16 * t + s];
-            const int64_t p = soff + idx[16 * t + s];
+        for (int s = 0; s < kStencil; ++s) {
+            const double wv = wts[(int64_t)kStencil * t + s];
+            const int64_t p = soff + idx[(int64_t)kStencil * t + s];
             for (int c = 0; c < 3; ++c) v[c] += wv * q[3 * p + c];
         }
     }
@@ -325,8 +329,8 @@ bool sphere_targets(const KeyMap &keys, const double *c, double a, double h, con
     x0.assign(3 * nt, 0.0);
     n0.assign(3 * nt, 0.0);
     b.assign(nt, 0.0);
-    idx.assign(16 * nt, 0);
-    wts.assign(16 * nt, 0.0);
+    idx.assign(kStencil * nt, 0);
+    wts.assign(kStencil * nt, 0.0);
     for (int64_t t = 0; t < nt; ++t) {
         if (t >= own0 && t < own1) {
             for (int d = 0; d < 3; ++d) {
@@ -348,11 +352,11 @@ bool sphere_targets(const KeyMap &keys, const double *c, double a, double h, con
             loc[e] = x0[3 * t + e] - c[e];
         }
         b[t] = r - a;
-        // widths 4, 3, 2; for each, families in decreasing |n_i| (ties: lower index first)
+        // widths 6 .. 2; for each, families in decreasing |n_i| (ties: lower index first)
         int fam[3] = {0, 1, 2};
         std::stable_sort(fam, fam + 3, [&](int u, int v2) { return std::fabs(loc[u]) > std::fabs(loc[v2]); });
         bool done = false;
-        for (int wdt = 4; wdt >= 2 && !done; --wdt) {
+        for (int wdt = kStencilWidth; wdt >= 2 && !done; --wdt) {
             for (int fi = 0; fi < 3 && !done; ++fi) {
                 const int i = fam[fi];
                 const int j = (i + 1) % 3 < (i + 2) % 3 ? (i + 1) % 3 : (i + 2) % 3;
@@ -360,7 +364,7 @@ bool sphere_targets(const KeyMap &keys, const double *c, double a, double h, con
                 const int sg = loc[i] > 0 ? 1 : -1;
                 const int64_t j0 = (int64_t)std::floor(loc[j] / h) - (wdt - 1) / 2;
                 const int64_t k0 = (int64_t)std::floor(loc[k] / h) - (wdt - 1) / 2;
-                int ids[16];
+                int ids[kStencil];
                 bool ok = true;
                 for (int aa = 0; aa < wdt && ok; ++aa)
                     for (int bb = 0; bb < wdt && ok; ++bb) {
@@ -374,8 +378,8 @@ bool sphere_targets(const KeyMap &keys, const double *c, double a, double h, con
                 const double sj = loc[j] / h - (double)j0, sk = loc[k] / h - (double)k0;
                 for (int aa = 0; aa < wdt; ++aa)
                     for (int bb = 0; bb < wdt; ++bb) {
-                        idx[16 * t + aa * wdt + bb] = ids[aa * wdt + bb];
-                        wts[16 * t + aa * wdt + bb] = lagrange(sj, aa, wdt) * lagrange(sk, bb, wdt);
+                        idx[kStencil * t + aa * wdt + bb] = ids[aa * wdt + bb];
+                        wts[kStencil * t + aa * wdt + bb] = lagrange(sj, aa, wdt) * lagrange(sk, bb, wdt);
                     }
                 done = true;
             }
@@ -594,13 +598,13 @@ sr_status sr_rigid_set_spheres(sr_rigid *R, int nsph, const double *centers, con
         RHIP(R->n0[m].alloc(3 * N));
         RHIP(R->b[m].alloc(N));
         RHIP(R->q0[m].alloc(3 * N));
-        RHIP(R->sidx[m].alloc(16 * N));
-        RHIP(R->swts[m].alloc(16 * N));
+        RHIP(R->sidx[m].alloc(kStencil * N));
+        RHIP(R->swts[m].alloc(kStencil * N));
         RHIP(hipMemcpyAsync(R->x0[m].p, hx0.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
         RHIP(hipMemcpyAsync(R->n0[m].p, hn0.data(), 3 * N * sizeof(double), hipMemcpyHostToDevice, s));
         RHIP(hipMemcpyAsync(R->b[m].p, hb.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
-        RHIP(hipMemcpyAsync(R->sidx[m].p, hidx.data(), 16 * N * sizeof(int), hipMemcpyHostToDevice, s));
-        RHIP(hipMemcpyAsync(R->swts[m].p, hwts.data(), 16 * N * sizeof(double), hipMemcpyHostToDevice, s));
+        RHIP(hipMemcpyAsync(R->sidx[m].p, hidx.data(), kStencil * N * sizeof(int), hipMemcpyHostToDevice, s));
+        RHIP(hipMemcpyAsync(R->swts[m].p, hwts.data(), kStencil * N * sizeof(double), hipMemcpyHostToDevice, s));
         RHIP(hipStreamSynchronize(s));
         sr_ctx *c2 = nullptr;
         RSR(sr_create(&c2, R->device));
@@ -699,8 +703,8 @@ sr_status sr_rigid_velocity(sr_rigid *R, const double *q, int64_t m, const doubl
     RHIP(dn0.alloc(3 * m));
     RHIP(db.alloc(m));
     RHIP(dq0.alloc(3 * m));
-    RHIP(dw.alloc(16 * m));
-    RHIP(di.alloc(16 * m));
+    RHIP(dw.alloc(kStencil * m));
+    RHIP(di.alloc(kStencil * m));
     for (int k = 0; k < R->nsph; ++k) {
         const int64_t o = R->off[k], nm = R->off[k + 1] - o;
         std::vector<double> hx0, hn0, hb, hwts;
@@ -711,8 +715,8 @@ sr_status sr_rigid_velocity(sr_rigid *R, const double *q, int64_t m, const doubl
         RHIP(hipMemcpyAsync(dx0.p, hx0.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
         RHIP(hipMemcpyAsync(dn0.p, hn0.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
         RHIP(hipMemcpyAsync(db.p, hb.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
-        RHIP(hipMemcpyAsync(di.p, hidx.data(), 16 * m * sizeof(int), hipMemcpyHostToDevice, s));
-        RHIP(hipMemcpyAsync(dw.p, hwts.data(), 16 * m * sizeof(double), hipMemcpyHostToDevice, s));
+        RHIP(hipMemcpyAsync(di.p, hidx.data(), kStencil * m * sizeof(int), hipMemcpyHostToDevice, s));
+        RHIP(hipMemcpyAsync(dw.p, hwts.data(), kStencil * m * sizeof(double), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(gather_q0_kernel, dim3(nblocks(m)), dim3(256), 0, s, q, m, (int64_t)0, (int64_t)0, o, di.p,
                            dw.p, dq0.p);
         RHIP(hipGetLastError());
@@ -1029,10 +1033,10 @@ sr_status sr_prolong_create(sr_prolong **out, int device, int nsph, const double
         if (!sphere_targets(keys, c, radii[m], hc, &hxf[3 * P->offf[m]], nf, 0, 0, nullptr, x0, n0, b, id, w))
             return rfail(SR_EINVAL, "sr_prolong_create: no interpolation stencil (is the coarse set the grid-line "
                                     "quadrature of the spheres with spacing hc?)");
-        RHIP(P->idx[m].alloc(16 * nf));
-        RHIP(P->wts[m].alloc(16 * nf));
-        RHIP(hipMemcpyAsync(P->idx[m].p, id.data(), 16 * nf * sizeof(int), hipMemcpyHostToDevice, s));
-        RHIP(hipMemcpyAsync(P->wts[m].p, w.data(), 16 * nf * sizeof(double), hipMemcpyHostToDevice, s));
+        RHIP(P->idx[m].alloc(kStencil * nf));
+        RHIP(P->wts[m].alloc(kStencil * nf));
+        RHIP(hipMemcpyAsync(P->idx[m].p, id.data(), kStencil * nf * sizeof(int), hipMemcpyHostToDevice, s));
+        RHIP(hipMemcpyAsync(P->wts[m].p, w.data(), kStencil * nf * sizeof(double), hipMemcpyHostToDevice, s));
         RHIP(hipStreamSynchronize(s));  // host staging vectors die at the end of the iteration
     }
     *out = guard.release();
