@@ -9,9 +9,11 @@
 // loss = mean over the batch and the P outputs of (o - y / s)^2; Adam (Kingma & Ba 2015).
 //
 // Matrix products: one kernel, C = A B^T with both operands stored K-contiguous as BF16, on
-// mfma_f32_16x16x32_bf16 with FP32 accumulation.  Each FP32 operand is carried as hi + lo, two
-// BF16 numbers (hi = bf16(x), lo = bf16(x - hi)); with passes = 3 the product sums hi*hi, hi*lo and
-// lo*hi (all on BF16 MFMA), which keeps about 16 significant bits instead of 8; passes = 1 uses hi*hi
+// mfma_f32_16x16x32_bf16 with FP32 accumulation.  Each FP32 operand is carried as hi + lo + lo2, three
+// BF16 numbers (hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi - lo): together the whole FP32
+// significand); with passes = 3 the product sums hi*hi, hi*lo and lo*hi (all on BF16 MFMA), which keeps
+// about 16 significant bits instead of 8; passes = 6 adds lo*lo, hi*lo2 and lo2*hi (about 24 bits, the
+// precision of the FP32 operands, at twice the matrix-core work); passes = 1 uses hi*hi
 // only.  Operands that a product needs transposed are kept as transposed BF16 copies, written by a
 // tiled LDS transpose as they are produced.  Leading dimensions and padded extents are multiples
 // of 32, padding is zero, so every fragment load is an aligned 16-byte load.
@@ -83,8 +85,9 @@ __device__ __forceinline__ float bf16_f(u16 b) { return __uint_as_float((uint32_
 
 template <int PASSES>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const u16 *__restrict__ Ahi, const u16 *__restrict__ Alo,
-                                                      int64_t lda, const u16 *__restrict__ Bhi,
-                                                      const u16 *__restrict__ Blo, int64_t ldb, int M, int N,
+                                                      const u16 *__restrict__ Alo2, int64_t lda,
+                                                      const u16 *__restrict__ Bhi, const u16 *__restrict__ Blo,
+                                                      const u16 *__restrict__ Blo2, int64_t ldb, int M, int N,
                                                       int Kpad, int kchunk, float *__restrict__ C, int64_t ldc,
                                                       int64_t split_stride)
 {
@@ -106,34 +109,50 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const u16 *__restrict__ Ah
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     // the operands of step k + kPad are loaded while step k's products run (register double buffer)
-    bf16x8 ah[2], bh[2], al[2], bl[2];
+    bf16x8 ah[2], bh[2], al[2], bl[2], a2[2], b2[2];
     auto load = [&](int k) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             ah[i] = *(const bf16x8 *)(Ahi + oa[i] + k);
             bh[i] = *(const bf16x8 *)(Bhi + ob[i] + k);
-            if (PASSES == 3) {
+            if (PASSES >= 3) {
                 al[i] = *(const bf16x8 *)(Alo + oa[i] + k);
                 bl[i] = *(const bf16x8 *)(Blo + ob[i] + k);
+            }
+            if (PASSES == 6) {
+                a2[i] = *(const bf16x8 *)(Alo2 + oa[i] + k);
+                b2[i] = *(const bf16x8 *)(Blo2 + ob[i] + k);
             }
         }
     };
     if (kb < ke) load(kb);
     for (int k = kb; k < ke; k += kPad) {
         const bf16x8 ch[2] = {ah[0], ah[1]}, dh[2] = {bh[0], bh[1]};
-        bf16x8 cl[2], dl[2];
-        if (PASSES == 3) {
+        bf16x8 cl[2], dl[2], c2[2], d2[2];
+        if (PASSES >= 3) {
             cl[0] = al[0];
             cl[1] = al[1];
             dl[0] = bl[0];
             dl[1] = bl[1];
         }
+        if (PASSES == 6) {
+            c2[0] = a2[0];
+            c2[1] = a2[1];
+            d2[0] = b2[0];
+            d2[1] = b2[1];
+        }
         if (k + kPad < ke) load(k + kPad);
+        // smallest terms first
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (PASSES == 3) {
+                if (PASSES == 6) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(c2[i], dh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[i], d2[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl[i], dl[j], acc[i][j], 0, 0, 0);
+                }
+                if (PASSES >= 3) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cl[i], dh[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ch[i], dl[j], acc[i][j], 0, 0, 0);
                 }
@@ -169,13 +188,14 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const float *part, int S,
     out[(int64_t)row * ldo + col] = s;
 }
 
-// X (R x Cc, FP32, ldx) -> hi/lo (rows < Rp, columns < Cp, ldh) and/or the transposes hiT/loT
-// (rows < Cp, columns < Rp, ldt); entries outside R x Cc are written as zero.  32 x 32 tiles through
-// LDS so that both the row-major and the transposed stores are coalesced.
+// X (R x Cc, FP32, ldx) -> hi/lo/lo2 (rows < Rp, columns < Cp, ldh) and/or the transposes
+// hiT/loT/lo2T (rows < Cp, columns < Rp, ldt); entries outside R x Cc are written as zero.  32 x 32
+// tiles through LDS so that both the row-major and the transposed stores are coalesced.  x - hi and
+// x - hi - lo are exact in FP32 (each difference has at most 16 significant bits).
 __global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ X, int R, int Cc, int64_t ldx, int Rp,
                                                       int Cp, u16 *__restrict__ hi, u16 *__restrict__ lo,
-                                                      int64_t ldh, u16 *__restrict__ hiT, u16 *__restrict__ loT,
-                                                      int64_t ldt)
+                                                      u16 *__restrict__ lo2, int64_t ldh, u16 *__restrict__ hiT,
+                                                      u16 *__restrict__ loT, u16 *__restrict__ lo2T, int64_t ldt)
 {
     __shared__ float tile[32][33];
     const int c0 = (int)blockIdx.x * 32, r0 = (int)blockIdx.y * 32;
@@ -186,8 +206,11 @@ __global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ 
         tile[k][tx] = v;
         if (hi && rr < Rp && cc < Cp) {
             const u16 h = bf16_rne(v);
+            const float r1 = v - bf16_f(h);
+            const u16 l = bf16_rne(r1);
             hi[(int64_t)rr * ldh + cc] = h;
-            lo[(int64_t)rr * ldh + cc] = bf16_rne(v - bf16_f(h));
+            lo[(int64_t)rr * ldh + cc] = l;
+            lo2[(int64_t)rr * ldh + cc] = bf16_rne(r1 - bf16_f(l));
         }
     }
     if (hiT) {  // uniform over the block
@@ -197,8 +220,11 @@ __global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ 
             if (cc < Cp && rr < Rp) {
                 const float v = tile[tx][k];
                 const u16 h = bf16_rne(v);
+                const float r1 = v - bf16_f(h);
+                const u16 l = bf16_rne(r1);
                 hiT[(int64_t)cc * ldt + rr] = h;
-                loT[(int64_t)cc * ldt + rr] = bf16_rne(v - bf16_f(h));
+                loT[(int64_t)cc * ldt + rr] = l;
+                lo2T[(int64_t)cc * ldt + rr] = bf16_rne(r1 - bf16_f(l));
             }
         }
     }
@@ -391,10 +417,18 @@ __global__ __launch_bounds__(256) void fill_u16_kernel(int64_t n, u16 *__restric
 
 // ---------------------------------------------------------------------------------------------
 
-struct Bf {  // one FP32 matrix as BF16 hi/lo, row-major, and optionally its transpose
-    u16 *hi = nullptr, *lo = nullptr, *hiT = nullptr, *loT = nullptr;
+struct Bf {  // one FP32 matrix as BF16 hi/lo/lo2, row-major, and optionally its transpose
+    u16 *hi = nullptr, *lo = nullptr, *lo2 = nullptr, *hiT = nullptr, *loT = nullptr, *lo2T = nullptr;
     int64_t ld = 0, ldT = 0;
 };
+
+// one GEMM operand: the three BF16 pieces of a K-contiguous matrix and its leading dimension
+struct Op {
+    const u16 *hi, *lo, *lo2;
+    int64_t ld;
+};
+inline Op rows_of(const Bf &b) { return Op{b.hi, b.lo, b.lo2, b.ld}; }
+inline Op cols_of(const Bf &b) { return Op{b.hiT, b.loT, b.lo2T, b.ldT}; }
 
 }  // namespace
 
@@ -437,44 +471,46 @@ struct sr_mlp {
 
 namespace {
 
-// hi/lo buffers (rows x ld) and transposes (cols x ldT), zero-filled
+// hi/lo/lo2 buffers (rows x ld) and transposes (cols x ldT), zero-filled
 sr_status alloc_bf(sr_mlp *M, Bf &b, int64_t rows, int64_t ld, int64_t cols, int64_t ldT, hipStream_t s)
 {
     b.ld = ld;
     b.ldT = ldT;
     if (rows > 0) {
-        MHIP(M->alloc(&b.hi, rows * ld));
-        MHIP(M->alloc(&b.lo, rows * ld));
-        hipLaunchKernelGGL(fill_u16_kernel, dim3(nblk(rows * ld)), dim3(256), 0, s, rows * ld, b.hi);
-        hipLaunchKernelGGL(fill_u16_kernel, dim3(nblk(rows * ld)), dim3(256), 0, s, rows * ld, b.lo);
+        for (u16 **q : {&b.hi, &b.lo, &b.lo2}) {
+            MHIP(M->alloc(q, rows * ld));
+            hipLaunchKernelGGL(fill_u16_kernel, dim3(nblk(rows * ld)), dim3(256), 0, s, rows * ld, *q);
+        }
     }
     if (cols > 0) {
-        MHIP(M->alloc(&b.hiT, cols * ldT));
-        MHIP(M->alloc(&b.loT, cols * ldT));
-        hipLaunchKernelGGL(fill_u16_kernel, dim3(nblk(cols * ldT)), dim3(256), 0, s, cols * ldT, b.hiT);
-        hipLaunchKernelGGL(fill_u16_kernel, dim3(nblk(cols * ldT)), dim3(256), 0, s, cols * ldT, b.loT);
+        for (u16 **q : {&b.hiT, &b.loT, &b.lo2T}) {
+            MHIP(M->alloc(q, cols * ldT));
+            hipLaunchKernelGGL(fill_u16_kernel, dim3(nblk(cols * ldT)), dim3(256), 0, s, cols * ldT, *q);
+        }
     }
     MHIP(hipGetLastError());
     return SR_OK;
 }
 
-// X (R x Cc) -> b.hi/lo over Rp x Cp and b.hiT/loT over Cp x Rp (those present)
+// X (R x Cc) -> b.hi/lo/lo2 over Rp x Cp and b.hiT/loT/lo2T over Cp x Rp (those present)
 sr_status convert(const float *X, int64_t R, int64_t Cc, int64_t ldx, int64_t Rp, int64_t Cp, const Bf &b,
                   bool rowmajor, bool transposed, hipStream_t s)
 {
     dim3 grid((unsigned)((Cp + 31) / 32), (unsigned)((Rp + 31) / 32));
     hipLaunchKernelGGL(convert_kernel, grid, dim3(256), 0, s, X, (int)R, (int)Cc, ldx, (int)Rp, (int)Cp,
-                       rowmajor ? b.hi : nullptr, rowmajor ? b.lo : nullptr, b.ld, transposed ? b.hiT : nullptr,
-                       transposed ? b.loT : nullptr, b.ldT);
+                       rowmajor ? b.hi : nullptr, rowmajor ? b.lo : nullptr, rowmajor ? b.lo2 : nullptr, b.ld,
+                       transposed ? b.hiT : nullptr, transposed ? b.loT : nullptr, transposed ? b.lo2T : nullptr,
+                       b.ldT);
     MHIP(hipGetLastError());
     return SR_OK;
 }
 
-// C (M x N) = A (M x Kpad) B^T (N x Kpad): A rows from (Ahi, Alo, lda), B rows from (Bhi, Blo, ldb).
+// C (M x N) = A (M x Kpad) B^T (N x Kpad): A and B row-major with K contiguous.
 // S > 1 splits K into S ranges written to M->part and summed by the epilogue.
-sr_status gemm(sr_mlp *Mo, const u16 *Ahi, const u16 *Alo, int64_t lda, const u16 *Bhi, const u16 *Blo, int64_t ldb,
-               int M, int N, int64_t Kpad, float *C, int64_t ldc, const float *bias, int act, int S, hipStream_t s)
+sr_status gemm(sr_mlp *Mo, const Op &A, const Op &B, int M, int N, int64_t Kpad, float *C, int64_t ldc,
+               const float *bias, int act, int S, hipStream_t s)
 {
+    const int64_t lda = A.ld, ldb = B.ld;
     if (Kpad % kPad != 0 || lda % 8 != 0 || ldb % 8 != 0 || M < 1 || N < 1 || (int64_t)M * N >= ((int64_t)1 << 31))
         return mfail(SR_EINVAL, "internal: gemm operand shapes");
     const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
@@ -493,12 +529,15 @@ sr_status gemm(sr_mlp *Mo, const u16 *Ahi, const u16 *Alo, int64_t lda, const u1
     if (S > 1 && (!Mo->part || sstride * S > (int64_t)Mo->Bpm * Mo->W * kMaxSplit))
         return mfail(SR_EINVAL, "internal: split buffer");
     dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64), (unsigned)S);
-    if (Mo->passes == 3)
-        hipLaunchKernelGGL(gemm_nt_kernel<3>, grid, dim3(256), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, (int)Kpad,
-                           (int)kchunk, dst, ldd, sstride);
+    if (Mo->passes == 6)
+        hipLaunchKernelGGL(gemm_nt_kernel<6>, grid, dim3(256), 0, s, A.hi, A.lo, A.lo2, lda, B.hi, B.lo, B.lo2, ldb,
+                           M, N, (int)Kpad, (int)kchunk, dst, ldd, sstride);
+    else if (Mo->passes == 3)
+        hipLaunchKernelGGL(gemm_nt_kernel<3>, grid, dim3(256), 0, s, A.hi, A.lo, A.lo2, lda, B.hi, B.lo, B.lo2, ldb,
+                           M, N, (int)Kpad, (int)kchunk, dst, ldd, sstride);
     else
-        hipLaunchKernelGGL(gemm_nt_kernel<1>, grid, dim3(256), 0, s, Ahi, Alo, lda, Bhi, Blo, ldb, M, N, (int)Kpad,
-                           (int)kchunk, dst, ldd, sstride);
+        hipLaunchKernelGGL(gemm_nt_kernel<1>, grid, dim3(256), 0, s, A.hi, A.lo, A.lo2, lda, B.hi, B.lo, B.lo2, ldb,
+                           M, N, (int)Kpad, (int)kchunk, dst, ldd, sstride);
     MHIP(hipGetLastError());
     if (S > 1 || bias || act) {
         hipLaunchKernelGGL(epilogue_kernel, dim3(nblk((int64_t)M * N)), dim3(256), 0, s, dst, S, sstride, M, N, ldd,
@@ -530,16 +569,15 @@ sr_status forward(sr_mlp *M, int B, const int64_t *idx, const double *g, const d
                        M->ghalf, blk(M, M->theta, PW1), blk(M, M->theta, PB1), W, M->gt, M->h1);
     MHIP(hipGetLastError());
     MSR(convert(M->h1, Bp, W, W, Bp, W, M->bh1, true, true, s));
-    MSR(gemm(M, M->bh1.hi, M->bh1.lo, W, M->w2.hi, M->w2.lo, W, Bp, W, W, M->h2, W, blk(M, M->theta, PB2), 1, 1, s));
+    MSR(gemm(M, rows_of(M->bh1), rows_of(M->w2), Bp, W, W, M->h2, W, blk(M, M->theta, PB2), 1, 1, s));
     MSR(convert(M->h2, Bp, W, W, Bp, W, M->bh2, true, true, s));
-    MSR(gemm(M, M->bh2.hi, M->bh2.lo, W, M->w3.hi, M->w3.lo, W, Bp, W, W, M->h3, W, blk(M, M->theta, PB3), 1, 1, s));
+    MSR(gemm(M, rows_of(M->bh2), rows_of(M->w3), Bp, W, W, M->h3, W, blk(M, M->theta, PB3), 1, 1, s));
     MSR(convert(M->h3, Bp, W, W, Bp, W, M->bh3, true, true, s));
-    MSR(gemm(M, M->bh3.hi, M->bh3.lo, W, M->w4.hi, M->w4.lo, W, Bp, K4, W, M->a4, K4, blk(M, M->theta, PB4), 0, 1,
-             s));
+    MSR(gemm(M, rows_of(M->bh3), rows_of(M->w4), Bp, K4, W, M->a4, K4, blk(M, M->theta, PB4), 0, 1, s));
     hipLaunchKernelGGL(contract_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, B, Bp, idx, mot, M->a4, W, M->z);
     MHIP(hipGetLastError());
     MSR(convert(M->z, Bp, W, W, Bp, W, M->bz, true, true, s));
-    MSR(gemm(M, M->bz.hi, M->bz.lo, W, M->wh.hi, M->wh.lo, W, Bp, (int)M->P, W, M->o, M->Pp, nullptr, 0, 1, s));
+    MSR(gemm(M, rows_of(M->bz), rows_of(M->wh), Bp, (int)M->P, W, M->o, M->Pp, nullptr, 0, 1, s));
     return SR_OK;
 }
 
@@ -556,40 +594,36 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
     MHIP(hipGetLastError());
     MSR(convert(M->dout, Bp, P, Pp, Bp, Pp, M->bdout, true, true, s));
     // head: dWh = dout^T z, dz = dout Wh
-    MSR(gemm(M, M->bdout.hiT, M->bdout.loT, M->bdout.ldT, M->bz.hiT, M->bz.loT, M->bz.ldT, (int)P, W, Bp,
-             blk(M, M->grad, PWH), W, nullptr, 0, 1, s));
+    MSR(gemm(M, cols_of(M->bdout), cols_of(M->bz), (int)P, W, Bp, blk(M, M->grad, PWH), W, nullptr, 0, 1, s));
     const int S = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, Pp / 512));
-    MSR(gemm(M, M->bdout.hi, M->bdout.lo, Pp, M->wh.hiT, M->wh.loT, M->wh.ldT, Bp, W, Pp, M->dz, W, nullptr, 0, S, s));
+    MSR(gemm(M, rows_of(M->bdout), cols_of(M->wh), Bp, W, Pp, M->dz, W, nullptr, 0, S, s));
     hipLaunchKernelGGL(contract_back_kernel, dim3(nblk((int64_t)Bp * K4)), dim3(256), 0, s, B, Bp, idx, mot, M->dz, W,
                        M->da4);
     MHIP(hipGetLastError());
     MSR(convert(M->da4, Bp, K4, K4, Bp, K4, M->bda4, true, true, s));
     // layer 4
-    MSR(gemm(M, M->bda4.hiT, M->bda4.loT, M->bda4.ldT, M->bh3.hiT, M->bh3.loT, M->bh3.ldT, K4, W, Bp,
-             blk(M, M->grad, PW4), W, nullptr, 0, 1, s));
+    MSR(gemm(M, cols_of(M->bda4), cols_of(M->bh3), K4, W, Bp, blk(M, M->grad, PW4), W, nullptr, 0, 1, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(nblk(K4)), dim3(256), 0, s, B, K4, M->da4, (int64_t)K4, blk(M, M->grad, PB4));
     MHIP(hipGetLastError());
-    MSR(gemm(M, M->bda4.hi, M->bda4.lo, K4, M->w4.hiT, M->w4.loT, M->w4.ldT, Bp, W, K4, M->dh, W, nullptr, 0, 1, s));
+    MSR(gemm(M, rows_of(M->bda4), cols_of(M->w4), Bp, W, K4, M->dh, W, nullptr, 0, 1, s));
     // layer 3
     hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, (int64_t)Bp * W, M->dh, M->h3,
                        M->d3);
     MHIP(hipGetLastError());
     MSR(convert(M->d3, Bp, W, W, Bp, W, M->bd3, true, true, s));
-    MSR(gemm(M, M->bd3.hiT, M->bd3.loT, M->bd3.ldT, M->bh2.hiT, M->bh2.loT, M->bh2.ldT, W, W, Bp,
-             blk(M, M->grad, PW3), W, nullptr, 0, 1, s));
+    MSR(gemm(M, cols_of(M->bd3), cols_of(M->bh2), W, W, Bp, blk(M, M->grad, PW3), W, nullptr, 0, 1, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(nblk(W)), dim3(256), 0, s, B, W, M->d3, (int64_t)W, blk(M, M->grad, PB3));
     MHIP(hipGetLastError());
-    MSR(gemm(M, M->bd3.hi, M->bd3.lo, W, M->w3.hiT, M->w3.loT, M->w3.ldT, Bp, W, W, M->dh, W, nullptr, 0, 1, s));
+    MSR(gemm(M, rows_of(M->bd3), cols_of(M->w3), Bp, W, W, M->dh, W, nullptr, 0, 1, s));
     // layer 2
     hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, (int64_t)Bp * W, M->dh, M->h2,
                        M->d2);
     MHIP(hipGetLastError());
     MSR(convert(M->d2, Bp, W, W, Bp, W, M->bd2, true, true, s));
-    MSR(gemm(M, M->bd2.hiT, M->bd2.loT, M->bd2.ldT, M->bh1.hiT, M->bh1.loT, M->bh1.ldT, W, W, Bp,
-             blk(M, M->grad, PW2), W, nullptr, 0, 1, s));
+    MSR(gemm(M, cols_of(M->bd2), cols_of(M->bh1), W, W, Bp, blk(M, M->grad, PW2), W, nullptr, 0, 1, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(nblk(W)), dim3(256), 0, s, B, W, M->d2, (int64_t)W, blk(M, M->grad, PB2));
     MHIP(hipGetLastError());
-    MSR(gemm(M, M->bd2.hi, M->bd2.lo, W, M->w2.hiT, M->w2.loT, M->w2.ldT, Bp, W, W, M->dh, W, nullptr, 0, 1, s));
+    MSR(gemm(M, rows_of(M->bd2), cols_of(M->w2), Bp, W, W, M->dh, W, nullptr, 0, 1, s));
     // layer 1 (the gap layer)
     hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, (int64_t)Bp * W, M->dh, M->h1,
                        M->d1);
@@ -765,7 +799,7 @@ sr_status sr_mlp_set_options(sr_mlp *M, int passes, double g_mid, double g_half)
 {
     g_merr.clear();
     if (!M) return mfail(SR_EINVAL, "sr_mlp_set_options: NULL network");
-    if (passes != 1 && passes != 3) return mfail(SR_EINVAL, "sr_mlp_set_options: passes must be 1 or 3");
+    if (passes != 1 && passes != 3 && passes != 6) return mfail(SR_EINVAL, "sr_mlp_set_options: passes must be 1, 3 or 6");
     if (!std::isfinite(g_mid) || !(g_half > 0.0) || !std::isfinite(g_half))
         return mfail(SR_EINVAL, "sr_mlp_set_options: need finite g_mid and g_half > 0");
     M->passes = passes;
@@ -951,7 +985,7 @@ sr_status sr_mlp_gemm_test(int device, int passes, int M, int N, int K, const fl
                            void *stream)
 {
     g_merr.clear();
-    if (passes != 1 && passes != 3) return mfail(SR_EINVAL, "sr_mlp_gemm_test: passes must be 1 or 3");
+    if (passes != 1 && passes != 3 && passes != 6) return mfail(SR_EINVAL, "sr_mlp_gemm_test: passes must be 1, 3 or 6");
     if (M < 1 || N < 1 || K < 1 || M > 65536 || N > 65536 || K > 65536 || !A || !Bm || !C)
         return mfail(SR_EINVAL, "sr_mlp_gemm_test: bad arguments");
     DevGuard g(device);
@@ -969,7 +1003,7 @@ sr_status sr_mlp_gemm_test(int device, int passes, int M, int N, int K, const fl
     if (st == SR_OK) st = alloc_bf(&T, b, N, Kp, 0, 0, s);
     if (st == SR_OK) st = convert(A, M, K, K, M, Kp, a, true, false, s);
     if (st == SR_OK) st = convert(Bm, N, K, K, N, Kp, b, true, false, s);
-    if (st == SR_OK) st = gemm(&T, a.hi, a.lo, Kp, b.hi, b.lo, Kp, M, N, Kp, C, N, nullptr, 0, 1, s);
+    if (st == SR_OK) st = gemm(&T, rows_of(a), rows_of(b), M, N, Kp, C, N, nullptr, 0, 1, s);
     (void)hipStreamSynchronize(s);
     for (void *p : T.allocs) (void)hipFree(p);
     return st;

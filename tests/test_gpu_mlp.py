@@ -1,8 +1,10 @@
 """Warm-start network and coarse-to-fine interpolation on the GPU, through the C ABI.
 
 - BF16 matrix-core product vs an FP64 product: |C - C_ref| <= tol * (|A| |B|^T) elementwise with
-  tol = 2^-8 (one pass: both operands rounded to BF16) or 2^-15 (three passes: hi*hi + hi*lo + lo*hi)
-  plus K 2^-23 for FP32 accumulation; ragged sizes and the head's shape;
+  tol = 2^-8 (one pass: both operands rounded to BF16), 2^-15 (three passes: hi*hi + hi*lo + lo*hi)
+  or 2^-25 (six passes: the whole FP32 operands, |lo| <= 2^-9 |x| and |lo2| <= 2^-18 |x|, so the
+  dropped lo*lo2, lo2*lo, lo2*lo2 are below 2^-26 |a||b|) plus K 2^-23 for FP32 accumulation;
+  ragged sizes and the head's shape;
 - forward outputs and loss gradients vs the numpy FP64 oracle (ragged batch and output count);
 - one Adam step vs the oracle's Adam applied to the kernel's own gradient;
 - padding rows never leak: a batch of 7 gives the same gradient through idx as the rows themselves;
@@ -48,7 +50,7 @@ def unflat(v, width, nout):
     return out
 
 
-@pytest.mark.parametrize("passes", [1, 3])
+@pytest.mark.parametrize("passes", [1, 3, 6])
 @pytest.mark.parametrize("mnk", [(70, 100, 300), (1, 33, 5), (64, 2000, 256), (64, 256, 4100)])
 def test_gemm_bound(P, passes, mnk):
     import torch
@@ -61,7 +63,7 @@ def test_gemm_bound(P, passes, mnk):
     P.sr_mlp_gemm_test(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), C, passes=passes)
     ref = A.astype(np.float64) @ B.astype(np.float64).T
     S = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64).T
-    tol = (2.0 ** -8 if passes == 1 else 2.0 ** -15) + k * 2.0 ** -23
+    tol = {1: 2.0 ** -8, 3: 2.0 ** -15, 6: 2.0 ** -25}[passes] + k * 2.0 ** -23
     ratio = (np.abs(C.cpu().numpy() - ref) / S).max()
     print(f"gemm {mnk} passes={passes}: max |err| / (|A||B|) = {ratio:.3e} (bound {tol:.2e})", flush=True)
     assert ratio <= tol
@@ -82,7 +84,7 @@ def setup_net(P, width, nout, batch, passes=3, seed=3):
     return net, p, g, m.reshape(batch, 12), y
 
 
-@pytest.mark.parametrize("passes", [3, 1])
+@pytest.mark.parametrize("passes", [3, 1, 6])
 def test_forward_matches_oracle(P, passes):
     width, nout, batch = 64, 301, 7
     net, p, g, m, _ = setup_net(P, width, nout, batch, passes)
@@ -90,7 +92,7 @@ def test_forward_matches_oracle(P, passes):
     ref = omlp.forward(p, g, m, GMID, GHALF)[0]
     e = np.abs(o - ref).max() / np.abs(ref).max()
     print(f"forward passes={passes}: {e:.3e}", flush=True)
-    assert e <= (1e-4 if passes == 3 else 2e-2)
+    assert e <= {3: 1e-4, 1: 2e-2, 6: 2e-6}[passes]
     net.close()
 
 
