@@ -23,7 +23,9 @@ Other workloads (--workload; each prints its own JSON line):
   mlp        the warm-start network at its real shape (width 256, 102420 outputs, batch 64): time of
              a training step by phase, and of one inference.
   warmstart  the learned warm start end to end: solves at h = 1/64 kept at the h = 1/32 points train
-             the network; held-out (gap, motion) pairs are solved from zero and from the prediction.
+             the network on the interaction part of the density (less the isolated spheres'); held-out
+             (gap, motion) pairs are solved from zero, from the isolated spheres' density, from the
+             network's prediction and from the training data interpolated in log(gap) (--ws-eval).
   table1     the paper's Table 1 workload: prolate spheroid x1^2 + 4 x2^2 + 4 x3^2 = 1, grid targets
              within h outside, single layer, rho = (3, 4, 5), h = 1/32 ... 1/256, direct far field.
   sweep      treecode parameters (theta, leaf size N0, degree p) at the h = 1/128 spheroid: time and
@@ -97,12 +99,32 @@ def parse():
                                            "peak"], default="c2")
     ap.add_argument("--no-gmres", action="store_true", help="c2: leave out the two-sphere GMRES solves")
     ap.add_argument("--drops-max", type=int, default=128, help="drops: finest 1/h")
-    ap.add_argument("--train-solves", type=int, default=792, help="warmstart: training solves")
-    ap.add_argument("--train-steps", type=int, default=500000, help="warmstart: optimizer steps")
-    ap.add_argument("--heldout", type=int, default=60, help="warmstart: held-out solves")
+    ap.add_argument("--train-solves", type=int, default=2004, help="warmstart: training solves")
+    ap.add_argument("--train-steps", type=int, default=20000, help="warmstart: optimizer steps")
+    ap.add_argument("--ws-batch", type=int, default=0, help="warmstart: Adam batch (0: every training solve)")
+    ap.add_argument("--ws-passes", type=int, default=6, choices=(1, 3, 6),
+                    help="warmstart: BF16 pieces products per matrix product of the network (6: FP32 accuracy)")
+    ap.add_argument("--ws-no-readout", action="store_true",
+                    help="warmstart: keep the output layers from Adam (no least-squares fit of them)")
+    ap.add_argument("--ws-data-tol", type=float, default=1e-7, help="warmstart: relative residual of the training solves")
+    ap.add_argument("--heldout", type=int, default=200, help="warmstart: held-out solves")
+    ap.add_argument("--heldout-stride", type=int, default=1,
+                    help="warmstart: solve every k-th of the held-out samples (the samples stay those of --heldout)")
     ap.add_argument("--ws-design", choices=("unit-log", "unit", "random"), default="unit",
                     help="warmstart: the 12 unit motions per gap at log-spaced or random gaps, or 4 random "
                          "motions per random gap")
+    ap.add_argument("--ws-eval", default="zero,iso,net,basis",
+                    help="warmstart: the starts solved for each held-out sample, comma-separated: zero, iso (the "
+                         "isolated spheres' density), net (network + isolated part), basis (the training data "
+                         "interpolated in log(gap) + isolated part)")
+    ap.add_argument("--ws-net", choices=("pod", "full"), default="pod",
+                    help="warmstart: the network predicts the coefficients of the training data's principal "
+                         "directions (pod) or every coarse value (full)")
+    ap.add_argument("--ws-save", default="", help="warmstart: write the trained model (and the training data's "
+                                                   "coefficients) to this directory")
+    ap.add_argument("--ws-load", default="", help="warmstart: evaluate a model written by --ws-save (no data, no training)")
+    ap.add_argument("--ws-no-iso", action="store_true",
+                    help="warmstart: train the network on the whole density (no isolated-sphere part)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (calibrates the FETCH_SIZE / WRITE_SIZE "
                          "counters against known bytes) and exit")
@@ -560,8 +582,9 @@ def bench_mlp(a):
 
 
 def bench_warmstart(a):
-    """Data from the library's own solves, training, and held-out solves from zero and from the
-    learned warm start."""
+    """Data from the library's own solves, training, and held-out solves from zero, from the learned
+    warm start and from two warm starts without learning (the isolated spheres' density; the training
+    data interpolated in log(gap))."""
     import torch
 
     import paper_2507_00156_amd as P
@@ -569,74 +592,166 @@ def bench_warmstart(a):
     from paper_2507_00156_amd import warmstart as W
 
     h_c, h_f, width = 1 / 32, 1 / 64, 256
-    if a.ws_design in ("unit", "unit-log"):
-        gaps, motions = workload.warmstart_unit_dataset(max(1, a.train_solves // 12), seed=21,
-                                                         spacing="log" if a.ws_design == "unit-log" else "random")
-    else:
-        gaps, motions = workload.warmstart_dataset(max(1, a.train_solves // 4), 4, seed=21)
+    methods = [m for m in a.ws_eval.split(",") if m]
+    bad = set(methods) - {"zero", "iso", "net", "basis"}
+    if bad:
+        raise SystemExit(f"--ws-eval: unknown {sorted(bad)}")
+    learned = "net" in methods or "basis" in methods
+    use_iso = not a.ws_no_iso
+    out_extra = {}
     t0 = time.perf_counter()
-    Y, its = W.generate(h_f, gaps, motions, tol=1e-6, log=log, keep=lambda g: W.restriction(h_c, h_f, g))
-    t_data = time.perf_counter() - t0
-    log(f"[bench warmstart] data: {len(gaps)} solves in {t_data:.0f} s (mean {its.mean():.1f} iterations)")
-    net = P.WarmStartNet(width, Y.shape[1], max_batch=64, passes=3)
-    net.set_params(np.concatenate([v.ravel() for v in workload.mlp_init(width, Y.shape[1], 5).values()])
-                   .astype(np.float32))
-    t0 = time.perf_counter()
-    hist = W.train(net, gaps, motions, Y, steps=a.train_steps, batch=64, lr=1e-3, seed=3, log=log,
-                   log_every=max(1, a.train_steps // 10))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del Y
-    ws = W.WarmStarter(net, h_c)
+    iso = W.IsolatedSphere(h_f) if (use_iso or "iso" in methods) else None
+    if iso is not None:
+        out_extra["isolated_basis_seconds"] = time.perf_counter() - t0
+        log(f"[bench warmstart] isolated-sphere basis: {iso.iterations} iterations, {time.perf_counter() - t0:.1f} s")
+    starters = {"zero": None}
+    if "iso" in methods:
+        starters["iso"] = W.WarmStarter(None, h_c, iso)
+    net = None
+    if learned and a.ws_load:
+        net, pod, gaps, motions, T, meta = W.load_model(a.ws_load)
+        out_extra.update(meta)
+        out_extra["loaded_from"] = os.path.basename(os.path.normpath(a.ws_load))
+        if "net" in methods:
+            starters["net"] = W.WarmStarter(W.network_predictor(net, pod), h_c, iso if use_iso else None)
+        if "basis" in methods:
+            starters["basis"] = W.WarmStarter(W.BasisInterpolator(gaps, T @ pod.V.T), h_c, iso if use_iso else None)
+        log(f"[bench warmstart] loaded {meta.get('training_solves')} training solves' model: {pod.r} modes")
+    elif learned:
+        if a.ws_design in ("unit", "unit-log"):
+            gaps, motions = workload.warmstart_unit_dataset(max(1, a.train_solves // 12), seed=21,
+                                                             spacing="log" if a.ws_design == "unit-log" else "random",
+                                                             ends=True)
+        else:
+            gaps, motions = workload.warmstart_dataset(max(1, a.train_solves // 4), 4, seed=21)
+        t0 = time.perf_counter()
+        Y, its = W.generate(h_f, gaps, motions, tol=a.ws_data_tol, log=log, keep=lambda g: W.restriction(h_c, h_f, g))
+        t_data = time.perf_counter() - t0
+        log(f"[bench warmstart] data: {len(gaps)} solves in {t_data:.0f} s (mean {its.mean():.1f} iterations)")
+        out_extra.update({"data_seconds": t_data, "data_iterations_mean": float(its.mean()),
+                          "training_solves": int(len(gaps))})
+        if use_iso:
+            for c0 in range(0, len(gaps), 256):
+                Y[c0:c0 + 256] -= W.coarse_isolated(iso, h_c, motions[c0:c0 + 256])
+        if "net" in methods:
+            pod, T, scale = None, Y, None
+            if a.ws_net == "pod":
+                t0 = time.perf_counter()
+                pod = W.PodDecoder(Y, rel=1e-7, rmax=width)
+                T = pod.encode(Y)
+                scale = torch.full((pod.r,), float(T.pow(2).mean().sqrt()), dtype=torch.float64, device="cuda")
+                out_extra.update({"pod_modes": pod.r, "pod_energy_tail": pod.energy_tail,
+                                  "pod_seconds": time.perf_counter() - t0})
+                log(f"[bench warmstart] principal directions: {pod.r} modes, energy beyond them {pod.energy_tail:.1e} "
+                    f"({time.perf_counter() - t0:.1f} s)")
+            bs = min(4096, len(gaps)) if a.ws_batch <= 0 else a.ws_batch
+            net = P.WarmStartNet(width, T.shape[1], max_batch=bs, passes=a.ws_passes)
+            net.set_params(np.concatenate([v.ravel() for v in workload.mlp_init(width, T.shape[1], 5).values()])
+                           .astype(np.float32))
+            t0 = time.perf_counter()
+            hist = W.train(net, gaps, motions, T, steps=a.train_steps, batch=bs, lr=1e-3, lr_min=1e-6, seed=3,
+                           log=log, log_every=max(1, a.train_steps // 10), scale=scale)
+            torch.cuda.synchronize()
+            out_extra.update({"train_seconds": time.perf_counter() - t0, "final_train_loss": hist[-1][1],
+                              "train_steps": a.train_steps, "train_batch": bs, "network_outputs": int(T.shape[1]),
+                              "network_passes": a.ws_passes})
+            if not a.ws_no_readout:
+                if a.ws_design == "random" or scale is None:
+                    raise SystemExit("the least-squares output layers need the unit-motion data and --ws-net pod")
+                t0 = time.perf_counter()
+                lam, loo, fit = W.fit_readout(net, gaps, T, scale, log=log)
+                out_extra.update({"readout_lambda": lam, "readout_leave_one_gap_out_rms": loo,
+                                  "readout_train_rms": fit, "readout_seconds": time.perf_counter() - t0})
+                log(f"[bench warmstart] least-squares output layers: lambda {lam:.1e}, leave-one-gap-out RMS {loo:.2e}, "
+                    f"training RMS {fit:.2e} (standardized)")
+            starters["net"] = W.WarmStarter(W.network_predictor(net, pod), h_c, iso if use_iso else None)
+            if a.ws_save:
+                W.save_model(a.ws_save, net, pod, gaps, motions, T,
+                             {k: out_extra[k] for k in ("training_solves", "data_seconds", "data_iterations_mean",
+                                                        "train_seconds", "final_train_loss", "train_steps", "train_batch",
+                                                        "network_outputs", "network_passes", "pod_modes",
+                                                        "pod_energy_tail", "readout_lambda",
+                                                        "readout_leave_one_gap_out_rms", "readout_train_rms")
+                              if k in out_extra} | {"passes": a.ws_passes, "ws_design": a.ws_design,
+                                                    "iso": use_iso, "data_tol": a.ws_data_tol})
+                log(f"[bench warmstart] model written to {a.ws_save}")
+        if "basis" in methods:
+            if a.ws_design == "random":
+                raise SystemExit("--ws-eval basis needs the unit-motion data (--ws-design unit or unit-log)")
+            starters["basis"] = W.WarmStarter(W.BasisInterpolator(gaps, Y), h_c, iso if use_iso else None)
+        if "basis" not in methods:
+            del Y
     tg, tm = workload.warmstart_samples(a.heldout, 77)
-    rows = []
-    for i, (g, m) in enumerate(zip(tg, tm)):
+    sel = list(range(0, len(tg), max(1, a.heldout_stride)))
+    rows = {m: [] for m in methods}
+    for c, i in enumerate(sel):
+        g, m = tg[i], tm[i]
         fine = W.TwoSpheres(h_f, g, precision=1)
         b = fine.R.rhs(m)
         try:  # builds the FP64 evaluators (set-up, untimed); 3 iterations do not converge
             fine.R.solve_refined(b, tol=1e-8, restart=100, maxit=3)
         except P.SrError:
             pass
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, i0, _, r0 = fine.R.solve_refined(b, tol=1e-8, restart=100)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        x0 = ws.guess(fine, m)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        _, i1, _, r1 = fine.R.solve_refined(b, x0=x0, tol=1e-8, restart=100)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        rows.append((g, i0, i1, t1 - t0, t3 - t1, t2 - t1, r0, r1))
-        log(f"[bench warmstart] held-out {i + 1}/{len(tg)} gap {g:.4f}: zero start {i0} iterations ({t1 - t0:.2f} s), "
-            f"warm start {i1} ({t3 - t1:.2f} s incl. {1e3 * (t2 - t1):.1f} ms prediction)")
+        msg, guesses, xs = [], {}, None
+        for name in methods:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x0 = None if starters[name] is None else starters[name].guess(fine, m)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, it, _, rr = fine.R.solve_refined(b, x0=x0, tol=1e-8, restart=100)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            guesses[name] = x0
+            xs = x if xs is None else xs
+            rows[name].append([g, it, t2 - t0, t1 - t0, rr, 0.0])
+            msg.append(f"{name} {it} ({t2 - t0:.2f} s)")
+        for name in methods:  # the start's distance from the solution, relative
+            x0 = guesses[name]
+            rows[name][-1][5] = 1.0 if x0 is None else ((x0 - xs).norm() / xs.norm()).item()
+        msg.append("start errors " + " ".join(f"{k} {rows[k][-1][5]:.1e}" for k in methods))
+        log(f"[bench warmstart] held-out {c + 1}/{len(sel)} (sample {i}) gap {g:.4f}: " + ", ".join(msg))
         fine.close()
-    r = np.array(rows)
-    ratio = r[:, 1].mean() / r[:, 2].mean()
+    R = {k: np.array(v) for k, v in rows.items()}
+    summary = {k: {"iterations_mean": float(v[:, 1].mean()), "seconds_mean": float(v[:, 2].mean()),
+                   "start_ms_mean": float(v[:, 3].mean() * 1e3), "max_final_residual": float(v[:, 4].max()),
+                   "start_error_median": float(np.median(v[:, 5])), "start_error_max": float(v[:, 5].max())}
+               for k, v in R.items()}
+    if "zero" in R:
+        for k, v in summary.items():
+            v["iteration_ratio_vs_zero"] = summary["zero"]["iterations_mean"] / v["iterations_mean"]
+            v["time_ratio_vs_zero"] = summary["zero"]["seconds_mean"] / v["seconds_mean"]
+    head = "net" if "net" in summary else methods[-1]
+    ratio = summary[head].get("iteration_ratio_vs_zero")
+    for k, v in summary.items():
+        log(f"[bench warmstart] {k}: mean {v['iterations_mean']:.1f} iterations, {v['seconds_mean']:.2f} s, start error "
+            f"median {v['start_error_median']:.1e}"
+            + (f", {v['iteration_ratio_vs_zero']:.2f}x fewer iterations than zero start" if "iteration_ratio_vs_zero" in v else ""))
+    ntr = out_extra.get("training_solves", 0)
     out = base_line("GMRES iterations from zero / from the learned warm start (FP64 residual 1e-8)", ratio,
-                    "x", len(rows), 0, float(r[:, 4].mean() * 1e3), True, "bf16 (hi/lo) network + f32/f64 solve",
+                    "x", len(sel), 0, summary[head]["seconds_mean"] * 1e3, True, "bf16 (hi/lo) network + f32/f64 solve",
                     "synthetic (two unit spheres, seeded gaps U[0.02,0.2] and N(0,1) rigid motions)",
-                    {"workload": f"warm start: {len(gaps)} training solves at h=1/64 kept at the h=1/32 points "
+                    {"workload": f"warm start: {ntr} training solves at h=1/64 kept at the h=1/32 points "
                                  + {"unit": "(the 12 unit motions at each of uniformly drawn gaps) ",
                                     "unit-log": "(the 12 unit motions at each of log-spaced gaps) ",
-                                    "random": "(4 random motions at each of uniformly drawn gaps) "}[a.ws_design] +
-                                 f"(102420 outputs), width 256, {a.train_steps} Adam steps; {len(rows)} held-out "
-                                 "solves at h=1/64 to FP64 residual 1e-8"})
+                                    "random": "(4 random motions at each of uniformly drawn gaps) "}[a.ws_design]
+                                 + ("network on the interaction part (density less the isolated spheres') "
+                                    if use_iso else "network on the whole density ")
+                                 + ("predicting the coefficients of the data's principal directions "
+                                    if a.ws_net == "pod" else "")
+                                 + f"(102420 coarse values), width 256, {a.train_steps} Adam steps"
+                                 + ("" if a.ws_no_readout else " then least-squares output layers")
+                                 + f", {a.ws_passes}-product BF16 matrix products; {len(sel)} held-out "
+                                 "solves at h=1/64 to FP64 residual 1e-8; starts: " + ", ".join(methods)})
     out["roofline"] = None
-    out["iterations_zero_mean"] = float(r[:, 1].mean())
-    out["iterations_warm_mean"] = float(r[:, 2].mean())
-    out["seconds_zero_mean"] = float(r[:, 3].mean())
-    out["seconds_warm_mean"] = float(r[:, 4].mean())
-    out["time_ratio"] = float(r[:, 3].mean() / r[:, 4].mean())
-    out["prediction_ms_mean"] = float(r[:, 5].mean() * 1e3)
-    out["max_final_residual"] = float(r[:, 6:8].max())
-    out["data_seconds"] = t_data
-    out["train_seconds"] = t_train
-    out["final_train_loss"] = hist[-1][1]
-    out["iterations_by_gap"] = [[float(x[0]), int(x[1]), int(x[2])] for x in rows]
+    out["starts"] = summary
+    out.update(out_extra)
+    out["iterations_by_sample"] = [[float(R[methods[0]][j, 0])] + [int(R[k][j, 1]) for k in methods]
+                                   for j in range(len(sel))]
+    out["iterations_by_sample_columns"] = ["gap"] + methods
     print(json.dumps(out), flush=True)
-    net.close()
+    if net is not None:
+        net.close()
 
 
 def _sl_setup(P, cfg, **kw):

@@ -238,6 +238,7 @@ class WarmStartNet:
     def __init__(self, width: int, nout: int, max_batch: int, passes: int = 3, g_mid: float = -2.760730458931123,
                  g_half: float = 1.151292546497023, device: int = 0):
         self.width, self.nout, self.max_batch = int(width), int(nout), int(max_batch)
+        self.g_mid, self.g_half = float(g_mid), float(g_half)
         self.net = B.sr_mlp_create(width, nout, max_batch, device)
         self.nparam = B.sr_mlp_num_params(width, nout)
         B.sr_mlp_set_options(self.net, passes, g_mid, g_half)
@@ -255,6 +256,7 @@ class WarmStartNet:
 
     def set_options(self, passes: int = 3, g_mid: float = -2.760730458931123, g_half: float = 1.151292546497023) -> None:
         B.sr_mlp_set_options(self.net, passes, g_mid, g_half)
+        self.g_mid, self.g_half = float(g_mid), float(g_half)
 
     def set_params(self, flat) -> None:
         B.sr_mlp_set_params(self.net, flat)

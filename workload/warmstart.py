@@ -41,16 +41,20 @@ def warmstart_dataset(n_gaps: int, per_gap: int, seed: int, gap_range=GAP_RANGE)
     return np.repeat(gaps, per_gap), motions
 
 
-def warmstart_unit_dataset(n_gaps: int, seed: int, gap_range=GAP_RANGE, spacing: str = "random"):
+def warmstart_unit_dataset(n_gaps: int, seed: int, gap_range=GAP_RANGE, spacing: str = "random",
+                           ends: bool = False):
     """n_gaps gaps in gap_range, each with the 12 unit rigid motions (one per parameter), so the
     solutions at one gap are the 12 columns of the solution map at that gap: (n_gaps * 12,) gaps and
     (n_gaps * 12, 2, 6) motions, the gaps repeated 12 times in a row.  spacing "random": uniform draws;
-    "log": the midpoints of n_gaps equal intervals of log(gap) (even cover of the network's input)."""
+    "log": the midpoints of n_gaps equal intervals of log(gap) (even cover of the network's input).
+    ends: the first two gaps are the ends of gap_range (the rest as drawn)."""
     rng = np.random.default_rng(seed)
     if spacing == "log":
         lo, hi = np.log(gap_range[0]), np.log(gap_range[1])
         gaps = np.exp(lo + (np.arange(n_gaps) + 0.5) / n_gaps * (hi - lo))
     else:
         gaps = rng.uniform(gap_range[0], gap_range[1], size=n_gaps)
+    if ends and n_gaps >= 2:
+        gaps[0], gaps[1] = gap_range[0], gap_range[1]
     motions = np.tile(np.eye(12).reshape(12, 2, 6), (n_gaps, 1, 1))
     return np.repeat(gaps, 12), motions
