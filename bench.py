@@ -67,9 +67,9 @@ TREE_FLOPS_PER_PROXY_PAIR = 75  # SL 24 + DL 40 + d, r^2, rsqrt, 1/r^2, 1/r^3 (1
 # HBM bytes per launch of the far-field kernels at this workload (FP64 and mixed), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE runs scaled by a copy calibration (profiles/far_near_c2_ellipsoid_h64.txt).
 # Valid only for the kernel sources they were measured on: reported as null once a source's hash differs.
-FAR_TRAFFIC = {"bytes": {"fp64": 1.068e8, "mixed": 9.786e7},
+FAR_TRAFFIC = {"bytes": {"fp64": 1.074e8, "mixed": 9.786e7},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
-                           "6b086652b476622e8e98cd422ed0556afc7712d2b9cc2799d7b853a8ef3f544e",
+                           "5f769e32b82e18b25269dc80e51b0771830f5c67136ac01102e174866ce8632a",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
                            "d3240416bf69c70873bd45e37c52add3523e6d799bd649ea616ebfc66be94756"}}
 
