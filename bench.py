@@ -71,7 +71,7 @@ FAR_TRAFFIC = {"bytes": {"fp64": 1.074e8, "mixed": 9.786e7},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "5f769e32b82e18b25269dc80e51b0771830f5c67136ac01102e174866ce8632a",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "d3240416bf69c70873bd45e37c52add3523e6d799bd649ea616ebfc66be94756"}}
+                           "2b7e1cc8e67be85a61d75c68e0f6be4b8ad92d1cb85f7fb89bdec66813a0a526"}}
 
 
 def far_traffic(precision):

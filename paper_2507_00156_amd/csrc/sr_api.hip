@@ -89,6 +89,12 @@ struct sr_ctx {
     DevBuf<double> part;  // far-field partial sums
     DevBuf<FrontierRec> t_front;
     DevBuf<double> stage;  // device copies of the caller's host arrays (SR_HOST)
+    // smoothing table of the targets on the surface (NearTable), built for tab_key = (sorted rho,
+    // cutoff, range); tab_ok false when its check failed (the kernels then use the closed forms)
+    DevBuf<double> near_tab;
+    std::vector<double> near_tab_host;
+    double tab_key[5] = {-1.0, -1.0, -1.0, -1.0, -1.0};
+    bool tab_ok = false;
     NearFlag *flag = nullptr;     // target-consistency report (sr_check), device memory
     double extent = 0.0;          // max over the points of max_d |x_d - org_d|
 
@@ -607,6 +613,34 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
     dp.rsharp = dp.sharp ? std::min(dp.rnear, c->prm.cutoff * c->prm.sharp_rho * c->prm.h) : dp.rnear;
     dp.reach = reach_of(c, dp.rnear, dp.rnear);
     dp.reach_sharp = reach_of(c, dp.rsharp, dp.rnear);
+    dp.ih = 1.0 / c->prm.h;
+    dp.ih3 = dp.ih * dp.ih * dp.ih;
+    dp.ih5 = dp.ih3 * dp.ih * dp.ih;
+    dp.tab = nullptr;
+    if (!u_delta && !v_delta && !dp.sharp) {
+        // the table covers r / h up to the near radius (and a little beyond, for the rounding of the
+        // pair test); built on the first evaluation with these parameters (not by the allocation-free
+        // call, which then uses the closed forms)
+        const double X = dp.rnear / c->prm.h * (1.0 + 1e-5);
+        const double key[5] = {dp.rho[0], dp.rho[1], dp.rho[2], dp.cutoff, X};
+        const bool same = std::equal(key, key + 5, c->tab_key);
+        if (!same && !noalloc) {
+            double err = 0.0;
+            c->tab_ok = build_near_table(dp.rho, dp.cutoff, X, c->near_tab_host, &err);
+            std::copy(key, key + 5, c->tab_key);
+            if (c->tab_ok) {
+                // synchronized: the host copy may be rebuilt by the next call with other parameters
+                SR_HIP(c->near_tab.reserve(kTabDoubles));
+                SR_HIP(hipMemcpyAsync(c->near_tab.p, c->near_tab_host.data(), kTabDoubles * sizeof(double),
+                                      hipMemcpyHostToDevice, s));
+                SR_HIP(hipStreamSynchronize(s));
+            }
+        }
+        if (std::equal(key, key + 5, c->tab_key) && c->tab_ok) {
+            dp.tab = c->near_tab.p;
+            dp.tab_scale = kTabIntervals / (X * c->prm.h);
+        }
+    }
 
     const bool tree = c->prm.far_method == SR_TREE;
     int nparts = kFarSplits;

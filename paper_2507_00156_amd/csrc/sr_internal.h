@@ -115,7 +115,26 @@ struct DevParams {
     int sharp;           // targets on the surface (b == 0) use the modified smoothing at one delta
     double inv_dsharp;   // 1 / that delta
     double rsharp;       // cutoff * that delta: the near radius of those targets (rnear otherwise)
+    // Smoothing table of the targets on the surface (b == 0) in the combined mode, or nullptr: see
+    // NearTable.  u = r * tab_scale in [0, kTabIntervals] indexes it; ih = 1 / h, ih3 = ih^3, ih5 = ih^5.
+    const double *tab;
+    double tab_scale, ih, ih3, ih5;
 };
+
+// Targets on the surface (b = 0) share one set of extrapolation weights (lambda_j = 0), so their
+// combined smoothing factors S_k(r) = sum_j w_j s_k(r / delta_j) are fixed functions of x = r / h.  The
+// table holds, on kTabIntervals equal intervals of x in [0, X] (X: the near radius over h, slightly
+// widened), the degree-kTabDegree interpolants in the local variable s in [-1/2, 1/2] of
+//   g1 = S1 / x,  g2 = S2 / x^3,  g3 = S3 / x^5
+// (finite and smooth at x = 0; (S2 - S3) / x^3 = g2 - x^2 g3).  Layout: coefficient k of function f on
+// interval i at tab[(f * kTabCoef + k) * kTabIntervals + i], so that the lanes of a wavefront, which
+// read the same coefficient of different intervals, hit different LDS banks.  S1/r = g1/h and so on.
+constexpr int kTabIntervals = 160, kTabDegree = 7, kTabCoef = kTabDegree + 1, kTabFuncs = 3;
+constexpr int kTabDoubles = kTabIntervals * kTabFuncs * kTabCoef;
+// Builds the table for the sorted smoothing ratios rho[3], the cut-off and the range X; returns false
+// (and leaves tab empty) if its interpolation error, checked against long-double evaluations, exceeds
+// 5e-14 of each function's largest value (6.5e-16 for rho = 2 : 3 : 4).  *maxerr: that error.
+bool build_near_table(const double rho[3], double cutoff, double X, std::vector<double> &tab, double *maxerr);
 
 // ---- kernel launchers (return hipSuccess or the launch error) ----
 hipError_t launch_pack(const double *x, const double *nrm, const double *w, const double *f, const double *q,

@@ -42,6 +42,10 @@
 // near regularization it skipped was needed: the scan reports it in the context's NearFlag.
 #include <math.h>
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include <type_traits>
 
 #include "sr_erfcx_table.h"
@@ -431,7 +435,7 @@ __device__ __forceinline__ void factors_one(double t, double cutoff, double &s1,
     dd = kD3 * (E * t) * (t * t);
 }
 
-enum { kModeComb = 0, kModePerDelta = 1, kModeSharp = 2 };
+enum { kModeComb = 0, kModePerDelta = 1, kModeSharp = 2, kModeTab = 3 };
 
 // The pairs the main pass leaves out (r below kSeriesT times the largest delta, r = 0 included):
 // every factor from the series or the closed form as t requires; r = 0 adds the limit of s1/r,
@@ -541,6 +545,51 @@ __device__ __forceinline__ void near_pair(const SrcRec<double> &s, const TgtV &T
     }
 }
 
+// One near pair of a target on the surface (b = 0) in the combined mode, from the smoothing table
+// (NearTable: S1/r, S2/r^3 and S3/r^5 as polynomials on 160 intervals of r / h, held in LDS;
+// (S2 - S3)/r^3 = S2/r^3 - r^2 S3/r^5).  No closed forms, no exponential and no series: the table is
+// smooth through r = 0 (the target's own point adds g S1/r at its limit), so every pair takes this one
+// path.  r = r2 / sqrt(r2) from the hardware estimate and one Newton step (relative error ~4e-15);
+// r = 0 exactly when r2 = 0.
+template <bool SL, bool DL>
+__device__ __forceinline__ void tab_pair(const SrcRec<double> &s, const TgtV &T, const DevParams &p,
+                                         const double *__restrict__ tabs, AccN<1> &A)
+{
+    const double dx = T.y[0] - s.x, dy = T.y[1] - s.y, dz = T.y[2] - s.z;
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    const double y = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-((0.5 * r2) * y), y, 1.5);
+    const double r = r2 > 0.0 ? r2 * (y * e) : 0.0;
+    const double u = r * p.tab_scale;
+    const int i = min((int)u, kTabIntervals - 1);
+    const double sv = u - (double)i - 0.5;
+    const double *c = tabs + i;
+    auto horner = [&](int f) {
+        const double *q = c + f * kTabCoef * kTabIntervals;
+        double v = q[kTabDegree * kTabIntervals];
+#pragma unroll
+        for (int k = kTabDegree - 1; k >= 0; --k) v = __builtin_fma(v, sv, q[k * kTabIntervals]);
+        return v;
+    };
+    const PairGeo G = pair_geo<SL, DL>(s, T, dx, dy, dz);
+    const double g2 = horner(1) * p.ih3;
+    if (SL) {
+        const double k1 = horner(0) * p.ih, k2 = G.dg * g2;
+        A.sl[0][0] = __builtin_fma(dx, k2, __builtin_fma(G.gx, k1, A.sl[0][0]));
+        A.sl[0][1] = __builtin_fma(dy, k2, __builtin_fma(G.gy, k1, A.sl[0][1]));
+        A.sl[0][2] = __builtin_fma(dz, k2, __builtin_fma(G.gz, k1, A.sl[0][2]));
+    }
+    if (DL) {
+        const double g3 = horner(2) * p.ih5;
+        const double k2 = __builtin_fma(-r2, g3, g2);  // (S2 - S3) / r^3
+        const double kd = __builtin_fma(G.nanm, k2, g3 * G.dadm);
+        A.dl[0][0] = __builtin_fma(dx, kd, A.dl[0][0]);
+        A.dl[0][1] = __builtin_fma(dy, kd, A.dl[0][1]);
+        A.dl[0][2] = __builtin_fma(dz, kd, A.dl[0][2]);
+        A.dn[0] = __builtin_fma(G.cn, k2, A.dn[0]);
+    }
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int l)
 {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
@@ -592,8 +641,13 @@ static_assert(kRing >= kWave - 1 + 4 * kWave && (kRing & (kRing - 1)) == 0, "rin
 // exact pass on those lanes.  The record is reloaded by the exact pass rather than kept.
 template <bool SL, bool DL, int MODE, bool P234, bool LO, int NJ>
 __device__ __forceinline__ void eval_pair(const SrcRec<double> *__restrict__ rec64, int k, const TgtV &T,
-                                          const DevParams &p, double rare2, AccN<NJ> &A)
+                                          const DevParams &p, double rare2, const double *__restrict__ tabs,
+                                          AccN<NJ> &A)
 {
+    if constexpr (MODE == kModeTab) {
+        tab_pair<SL, DL>(rec64[k], T, p, tabs, A);
+        return;
+    }
     bool rare;
     near_pair<SL, DL, MODE, P234, LO, NJ>(rec64[k], T, p, rare2, A, rare);
     if (__ballot(rare) && rare) {
@@ -628,13 +682,26 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
     // single-precision candidate test = the mixed-precision path: the degree-11 erfcx table
     constexpr bool kLo = std::is_same<TC, float>::value;
     constexpr bool SHARP = MODE == kModeSharp;
+    constexpr bool TAB = MODE == kModeTab;
     constexpr int NJ = MODE == kModePerDelta ? 3 : 1;
     __shared__ int queue_all[kBlock / kWave][kRing];
+    __shared__ double2 tab_all[TAB ? kTabDoubles / 2 : 1];
+    const double *tabs = reinterpret_cast<const double *>(tab_all);
     // readfirstlane: the wave index (hence the target) is wavefront-uniform
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int lane = (int)threadIdx.x % kWave;
     int *queue = queue_all[wave];
     const int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
+    if constexpr (TAB) {
+        // the workgroup copies the smoothing table into LDS if any of its targets is on the surface;
+        // every wave reaches the barriers before leaving
+        const bool mine = t < a.m && a.b[t] == 0.0;
+        if (!__syncthreads_or(mine)) return;
+        const double2 *src = reinterpret_cast<const double2 *>(p.tab);
+        for (int k = (int)threadIdx.x; k < kTabDoubles / 2; k += kBlock) tab_all[k] = src[k];
+        __syncthreads();
+        if (!mine) return;
+    }
     if (t >= a.m) return;  // wavefront-uniform exit
 
     double ty[3], tn[3], tq0[3];
@@ -649,6 +716,8 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
     // SHARP instance takes exactly these targets, the others every other target (wavefront-uniform)
     const bool sharp = p.sharp && tb == 0.0;
     if (sharp != SHARP) return;
+    // with the smoothing table the TAB instance takes the targets on the surface
+    if (MODE == kModeComb && p.tab != nullptr && tb == 0.0) return;
     const double tc = SL ? a.f0[3 * t] * tn[0] + a.f0[3 * t + 1] * tn[1] + a.f0[3 * t + 2] * tn[2] : 0.0;
     double w[3] = {1.0, 0.0, 0.0};
     if (MODE == kModeComb) extrap_weights_wave(tb, p, lane, w);
@@ -754,13 +823,14 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
                     wave_lds_sync();
                     head = (head + kWave) & (kRing - 1);
                     cnt -= kWave;
-                    eval_pair<SL, DL, MODE, P234, kLo, NJ>(rec64, k2, T, p, rare2, A);
+                    eval_pair<SL, DL, MODE, P234, kLo, NJ>(rec64, k2, T, p, rare2, tabs, A);
                 }
             }
         }
     }
     wave_lds_sync();
-    if (lane < cnt) eval_pair<SL, DL, MODE, P234, kLo, NJ>(rec64, queue[(head + lane) & (kRing - 1)], T, p, rare2, A);
+    if (lane < cnt)
+        eval_pair<SL, DL, MODE, P234, kLo, NJ>(rec64, queue[(head + lane) & (kRing - 1)], T, p, rare2, tabs, A);
     if (farrule && __ballot(bad) && lane == 0) {
         atomicOr(&flag->bits, kFlagFarRule);
         atomicMin(&flag->first, (unsigned long long)t);
@@ -856,7 +926,13 @@ hipError_t launch_t(const SrcRec<double> *rec64, const Pos4<TC> *pos, const int 
         hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModePerDelta, false>), grid, block, 0, s, rec64, pos,
                            cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !p.sharp) return e;
+    if (e != hipSuccess) return e;
+    if (p.tab != nullptr) {  // set only for the combined mode without the modified smoothing
+        hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModeTab, false>), grid, block, 0, s, rec64, pos,
+                           cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
+        return hipGetLastError();
+    }
+    if (!p.sharp) return hipSuccess;
     hipLaunchKernelGGL((near_finalize_kernel<TC, SL, DL, kModeSharp, false>), grid, block, 0, s, rec64, pos,
                        cell_start, g, a, p, rc2, rc2s, part, nparts, flag);
     return hipGetLastError();
@@ -946,6 +1022,148 @@ hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> 
     if (precision == SR_MIXED)
         return dispatch<float>(layers, rec64, pos32, cell_start, grid, a, p, (float)rc2, part, nparts, flag, s);
     return dispatch<double>(layers, rec64, pos64, cell_start, grid, a, p, rc2, part, nparts, flag, s);
+}
+
+// ---- the smoothing table of the targets on the surface (NearTable in sr_internal.h) ----
+namespace {
+
+// s1 / t, s2 / t^3, s3 / t^5 and e^{-t^2} at t >= 0 in long double (eqs. (s1)-(s3): s1 = erf t,
+// s2 = erf t - (2/sqrt(pi)) t e^{-t^2}, s3 = s2 - (4/(3 sqrt(pi))) t^3 e^{-t^2}); Maclaurin series below
+// t = 1 (the differences lose the relative accuracy of s2 ~ t^3 and s3 ~ t^5 there), closed forms above.
+void smoothing_ratios_ld(long double t, long double &r1, long double &r2, long double &r3, long double &E)
+{
+    const long double c = 1.128379167095512573896158903121545172L;  // 2 / sqrt(pi)
+    E = expl(-t * t);
+    if (t < 1.0L) {
+        const long double t2 = t * t;
+        long double f = 1.0L, p = 1.0L, a1 = 0.0L, a2 = 0.0L, a3 = 0.0L;  // f = (-1)^n / n!, p = t^2n
+        for (int n = 0; n < 40; ++n) {
+            a1 += f * p / (2 * n + 1);
+            a2 += 2.0L * f * p / (2 * n + 3);
+            a3 += 4.0L * f * p / (3.0L * (2 * n + 5));
+            f = -f / (n + 1);
+            p *= t2;
+        }
+        r1 = c * a1;
+        r2 = c * a2;
+        r3 = c * a3;
+        return;
+    }
+    const long double s1 = erfl(t);
+    const long double s2 = s1 - c * t * E;
+    const long double s3 = s2 - (2.0L / 3.0L) * c * t * t * t * E;
+    r1 = s1 / t;
+    r2 = s2 / (t * t * t);
+    r3 = s3 / (t * t * t * t * t);
+}
+
+// g1, g2, g3 at x = r / h (see NearTable) for the weights w of the sorted ratios rho
+void table_functions_ld(long double x, const long double rho[3], const long double w[3], long double cutoff,
+                        long double g[kTabFuncs])
+{
+    g[0] = g[1] = g[2] = 0.0L;
+    for (int j = 0; j < 3; ++j) {
+        const long double t = x / rho[j];
+        if (t > cutoff) {  // s_k = 1 beyond the cut-off (paper section 3.2); x > 0 here
+            g[0] += w[j] / x;
+            g[1] += w[j] / (x * x * x);
+            g[2] += w[j] / (x * x * x * x * x);
+            continue;
+        }
+        long double r1, r2, r3, E;
+        smoothing_ratios_ld(t, r1, r2, r3, E);
+        const long double p1 = rho[j], p3 = p1 * p1 * p1, p5 = p3 * p1 * p1;
+        g[0] += w[j] * r1 / p1;
+        g[1] += w[j] * r2 / p3;
+        g[2] += w[j] * r3 / p5;
+    }
+}
+
+}  // namespace
+
+bool build_near_table(const double rho_d[3], double cutoff, double X, std::vector<double> &tab, double *maxerr)
+{
+    tab.clear();
+    *maxerr = 0.0;
+    long double rho[3], w[3];
+    for (int j = 0; j < 3; ++j) rho[j] = rho_d[j];
+    // extrapolation weights at b = 0 (eq. (extrap_eqn)): rows [1, rho_j I0(0), rho_j^3 I2(0)] with
+    // I0(0) = 1/sqrt(pi), I2(0) = 1/(3 sqrt(pi)); w = e_1^T A^{-1} by Cramer's rule (the common factor
+    // 1/sqrt(pi) cancels)
+    long double al[3], be[3];
+    for (int j = 0; j < 3; ++j) {
+        al[j] = rho[j];
+        be[j] = rho[j] * rho[j] * rho[j] / 3.0L;
+    }
+    const long double C0 = al[1] * be[2] - al[2] * be[1], C1 = al[2] * be[0] - al[0] * be[2],
+                      C2 = al[0] * be[1] - al[1] * be[0];
+    const long double D = C0 + C1 + C2;
+    if (!(fabsl(D) > 0.0L) || !(X > 0.0)) return false;
+    w[0] = C0 / D;
+    w[1] = C1 / D;
+    w[2] = C2 / D;
+    const long double dx = (long double)X / kTabIntervals, pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> t((size_t)kTabDoubles);
+    long double gmax[kTabFuncs] = {0.0L, 0.0L, 0.0L};
+    // interpolation at the Chebyshev points of each interval, monomial coefficients in s
+    for (int i = 0; i < kTabIntervals; ++i) {
+        long double V[kTabCoef][kTabCoef], F[kTabFuncs][kTabCoef];
+        for (int k = 0; k < kTabCoef; ++k) {
+            const long double sk = 0.5L * cosl((2 * k + 1) * pi / (2 * kTabCoef));
+            long double g[kTabFuncs];
+            table_functions_ld(dx * (i + 0.5L + sk), rho, w, cutoff, g);
+            long double pw = 1.0L;
+            for (int e = 0; e < kTabCoef; ++e) {
+                V[k][e] = pw;
+                pw *= sk;
+            }
+            for (int f = 0; f < kTabFuncs; ++f) {
+                F[f][k] = g[f];
+                gmax[f] = std::max(gmax[f], fabsl(g[f]));
+            }
+        }
+        // Gaussian elimination with partial pivoting, one right-hand side per function
+        for (int col = 0; col < kTabCoef; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < kTabCoef; ++r)
+                if (fabsl(V[r][col]) > fabsl(V[piv][col])) piv = r;
+            if (piv != col) {
+                for (int e = 0; e < kTabCoef; ++e) std::swap(V[col][e], V[piv][e]);
+                for (int f = 0; f < kTabFuncs; ++f) std::swap(F[f][col], F[f][piv]);
+            }
+            for (int r = col + 1; r < kTabCoef; ++r) {
+                const long double m = V[r][col] / V[col][col];
+                for (int e = col; e < kTabCoef; ++e) V[r][e] -= m * V[col][e];
+                for (int f = 0; f < kTabFuncs; ++f) F[f][r] -= m * F[f][col];
+            }
+        }
+        for (int f = 0; f < kTabFuncs; ++f)
+            for (int r = kTabCoef - 1; r >= 0; --r) {
+                long double acc = F[f][r];
+                for (int e = r + 1; e < kTabCoef; ++e) acc -= V[r][e] * F[f][e];
+                F[f][r] = acc / V[r][r];
+                t[((size_t)f * kTabCoef + r) * kTabIntervals + i] = (double)F[f][r];
+            }
+    }
+    // check: the double-precision Horner evaluation the kernel performs against long double, at 17
+    // points per interval (both ends included)
+    long double err = 0.0L;
+    for (int i = 0; i < kTabIntervals; ++i)
+        for (int q = 0; q <= 16; ++q) {
+            const double sv = -0.5 + q / 16.0;
+            long double g[kTabFuncs];
+            table_functions_ld(dx * (i + 0.5L + sv), rho, w, cutoff, g);
+            for (int f = 0; f < kTabFuncs; ++f) {
+                const double *c = &t[(size_t)f * kTabCoef * kTabIntervals + i];
+                double v = c[kTabDegree * kTabIntervals];
+                for (int e = kTabDegree - 1; e >= 0; --e) v = std::fma(v, sv, c[e * kTabIntervals]);
+                err = std::max(err, fabsl((long double)v - g[f]) / gmax[f]);
+            }
+        }
+    *maxerr = (double)err;
+    if (!(err <= 5e-14L)) return false;
+    tab.swap(t);
+    return true;
 }
 
 }  // namespace sr

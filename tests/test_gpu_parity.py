@@ -265,3 +265,34 @@ def test_concurrent_phases_equal_serial(P, small, precision, far):
         e2 = rel_err(vk.cpu().numpy(), serial[k][1])
         print(f"concurrent {far} prec={precision} k={k}: SL {e1:.2e} DL {e2:.2e}", flush=True)
         assert e1 <= 1e-13 and e2 <= 1e-13
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_surface_table_equals_closed_forms(P, small, precision):
+    """Targets on the surface (b = 0) take the smoothing table in the combined mode and the closed forms
+    of eqs. (s1)-(s3) when the per-delta values are asked for; the extrapolated values agree to the
+    table's accuracy in double precision (1e-12 relative) and, on the mixed path, to that of the closed
+    forms' degree-11 erfcx interpolant (|erfc error| <= 1.6e-11, so <= 2e-9 in u)."""
+    cfg, _ = small
+    on = np.nonzero(cfg["targets"].b == 0.0)[0]
+    assert len(on) > 100
+    u1, v1 = gpu_eval(cfg, P.SR_SL | P.SR_DL, precision)[:2]
+    u2, v2 = gpu_eval(cfg, P.SR_SL | P.SR_DL, precision, want_delta=True)[:2]
+    e1, e2 = rel_err(u1[on], u2[on]), rel_err(v1[on], v2[on])
+    print(f"table vs closed forms prec={precision}: SL {e1:.2e} DL {e2:.2e}", flush=True)
+    bar = 1e-12 if precision == 0 else 2e-9
+    assert e1 <= bar and e2 <= bar
+
+
+def test_surface_targets_without_table_match_oracle(P, small):
+    """With rho = 1 : 2 : 3 the smoothing table misses its accuracy check (the smallest delta is h) and
+    the surface targets take the closed forms in the combined mode; parity with the oracle."""
+    cfg, _ = small
+    cfg = dict(cfg, rho=(1.0, 2.0, 3.0))
+    u = oracle.sl_cfg(cfg)
+    v = oracle.dl_cfg(cfg)
+    for precision in (0, 1):
+        gu, gv = gpu_eval(cfg, P.SR_SL | P.SR_DL, precision)[:2]
+        e1, e2 = rel_err(gu, u), rel_err(gv, v)
+        print(f"rho 1:2:3 prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
+        assert e1 <= TOL[precision] and e2 <= TOL[precision]
