@@ -644,8 +644,13 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
 
     const bool tree = c->prm.far_method == SR_TREE;
     int nparts = kFarSplits;
-    if (tree) {
-        if ((st = ensure_tree(c, s)) != SR_OK) return st;
+    if (tree && (st = ensure_tree(c, s)) != SR_OK) return st;
+    // A Morton order of the targets, those on the surface first (DevParams::order): the treecode walks
+    // in it and the near-field kernel takes the targets in it.  Not made by the allocation-free call
+    // (the caller's order).
+    const bool order = tree || !noalloc;
+    dp.order = nullptr;
+    if (order) {
         TreeDev &D = c->tdev;
         SR_HIP(c->t_key_in.reserve(m));
         SR_HIP(c->t_key_out.reserve(m));
@@ -659,7 +664,20 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
         D.order = c->t_order.p;
         D.sort_tmp = c->t_sort_tmp.p;
         D.sort_tmp_bytes = c->t_sort_tmp.cap;
-        nparts = c->tdev.nfront;
+        dp.order = D.order;
+    }
+    if (tree) nparts = c->tdev.nfront;
+    // Morton box: the treecode's root box, or the cell grid's, widened by the near radius
+    double mlo[3], mext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (tree) {
+            const TreeNode &root = c->tree.nodes[0];
+            mlo[d] = root.lo[d] - dp.rnear;
+            mext = std::max(mext, root.hi[d] - root.lo[d] + 2.0 * dp.rnear);
+        } else {
+            mlo[d] = c->grid.lo[d] - dp.rnear;
+            mext = std::max(mext, c->grid.g[d] * c->grid.side + 2.0 * dp.rnear);
+        }
     }
     double *part;
     if (noalloc) {
@@ -677,18 +695,11 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
     // time (the no-alloc variant records no events: it runs the phases concurrently).
     const bool profile = c->profiling && !noalloc;
     const bool concurrent = !profile && !u_delta && !v_delta;
+    // the target order (1024 steps per axis) before both phases, which read it
+    if (order) SR_HIP(launch_target_order(y, b, (int)m, mlo, 1024.0 / mext, c->tdev, s));
     if (concurrent) SR_HIP(hipEventRecord(c->ev_fork, s));
     if (profile && (st = record_event(c, s)) != SR_OK) return st;
     if (tree) {
-        // Morton order over the sources' cell grid box, 1024 steps per axis
-        const TreeNode &root = c->tree.nodes[0];
-        double ext = 0.0;
-        double lo[3];
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = root.lo[d] - dp.rnear;
-            ext = std::max(ext, root.hi[d] - root.lo[d] + 2.0 * dp.rnear);
-        }
-        SR_HIP(launch_target_order(y, (int)m, lo, 1024.0 / ext, c->tdev, s));
         SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear, dp.rsharp, dp.sharp,
                                part, s));
     } else {

@@ -119,6 +119,12 @@ struct DevParams {
     // NearTable.  u = r * tab_scale in [0, kTabIntervals] indexes it; ih = 1 / h, ih3 = ih^3, ih5 = ih^5.
     const double *tab;
     double tab_scale, ih, ih3, ih5;
+    // Order in which the near-field wavefronts take the targets, or nullptr for the caller's order:
+    // the targets on the surface first, then the others, each part in Morton order, so that a
+    // workgroup's four targets are neighbours and belong to the same launch (the smoothing-table
+    // launch takes the first part, the closed-form launch the second), and the workgroups resident
+    // at one time cover a compact piece of the surface, whose source records stay in the L2s.
+    const int *order;
 };
 
 // Targets on the surface (b = 0) share one set of extrapolation weights (lambda_j = 0), so their

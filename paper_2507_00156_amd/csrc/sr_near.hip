@@ -691,7 +691,10 @@ __global__ __launch_bounds__(kBlock) void near_finalize_kernel(const SrcRec<doub
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int lane = (int)threadIdx.x % kWave;
     int *queue = queue_all[wave];
-    const int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
+    // the target of this wavefront: slot-th in the target order (see DevParams::order)
+    const int64_t slot = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
+    const int64_t t =
+        (p.order != nullptr && slot < a.m) ? (int64_t)__builtin_amdgcn_readfirstlane(p.order[slot]) : slot;
     if constexpr (TAB) {
         // the workgroup copies the smoothing table into LDS if any of its targets is on the surface;
         // every wave reaches the barriers before leaving

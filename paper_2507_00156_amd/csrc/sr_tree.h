@@ -75,7 +75,10 @@ hipError_t launch_anterp(const TreeDev &D, const double *cosk, double *partial, 
 
 // Sort targets by a 30-bit Morton key of their position quantized in [lo, lo + 1024/inv); D.order
 // receives the sorted target indices.
-hipError_t launch_target_order(const double *y, int m, const double lo[3], double inv, TreeDev &D, hipStream_t s);
+// b (nullable): the targets' signed distances; those with b != 0 then follow those with b == 0 (each
+// part in Morton order).
+hipError_t launch_target_order(const double *y, const double *b, int m, const double lo[3], double inv, TreeDev &D,
+                               hipStream_t s);
 size_t target_sort_tmp_bytes(int m);
 
 // Far field by the treecode into part[split][channel][target], D.nfront splits.

@@ -390,8 +390,8 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v)
     return v;
 }
 
-__global__ __launch_bounds__(kBlock) void morton_kernel(const double *y, int m, double lox, double loy, double loz,
-                                                        double inv, uint32_t *key, int *idx)
+__global__ __launch_bounds__(kBlock) void morton_kernel(const double *y, const double *b, int m, double lox,
+                                                        double loy, double loz, double inv, uint32_t *key, int *idx)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= m) return;
@@ -403,7 +403,8 @@ __global__ __launch_bounds__(kBlock) void morton_kernel(const double *y, int m, 
         u = fmin(fmax(u, 0.0), 1023.0);
         q[d] = (uint32_t)u;
     }
-    key[t] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    const uint32_t off = (b != nullptr && b[t] != 0.0) ? (1u << 30) : 0u;
+    key[t] = off | spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
     idx[t] = t;
 }
 
@@ -661,21 +662,22 @@ hipError_t launch_anterp(const TreeDev &D, const double *cosk, double *partial, 
     return hipGetLastError();
 }
 
-hipError_t launch_target_order(const double *y, int m, const double lo[3], double inv, TreeDev &D, hipStream_t s)
+hipError_t launch_target_order(const double *y, const double *b, int m, const double lo[3], double inv, TreeDev &D,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(morton_kernel, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, y, m, lo[0], lo[1], lo[2],
-                       inv, D.key_in, D.idx_in);
+    hipLaunchKernelGGL(morton_kernel, dim3((m + kBlock - 1) / kBlock), dim3(kBlock), 0, s, y, b, m, lo[0], lo[1],
+                       lo[2], inv, D.key_in, D.idx_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t bytes = D.sort_tmp_bytes;
-    return hipcub::DeviceRadixSort::SortPairs(D.sort_tmp, bytes, D.key_in, D.key_out, D.idx_in, D.order, m, 0, 30, s);
+    return hipcub::DeviceRadixSort::SortPairs(D.sort_tmp, bytes, D.key_in, D.key_out, D.idx_in, D.order, m, 0, 31, s);
 }
 
 size_t target_sort_tmp_bytes(int m)
 {
     size_t bytes = 0;
     (void)hipcub::DeviceRadixSort::SortPairs((void *)nullptr, bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                       (int *)nullptr, (int *)nullptr, m, 0, 30);
+                                       (int *)nullptr, (int *)nullptr, m, 0, 31);
     return bytes;
 }
 
