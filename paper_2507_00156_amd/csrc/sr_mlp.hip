@@ -189,7 +189,8 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const float *part, int S,
 }
 
 // X (R x Cc, FP32, ldx) -> hi/lo/lo2 (rows < Rp, columns < Cp, ldh) and/or the transposes
-// hiT/loT/lo2T (rows < Cp, columns < Rp, ldt); entries outside R x Cc are written as zero.  32 x 32
+// hiT/loT/lo2T (rows < Cp, columns < Rp, ldt; lo2 / lo2T may be null); entries outside R x Cc are
+// written as zero.  32 x 32
 // tiles through LDS so that both the row-major and the transposed stores are coalesced.  x - hi and
 // x - hi - lo are exact in FP32 (each difference has at most 16 significant bits).
 __global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ X, int R, int Cc, int64_t ldx, int Rp,
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ 
             const u16 l = bf16_rne(r1);
             hi[(int64_t)rr * ldh + cc] = h;
             lo[(int64_t)rr * ldh + cc] = l;
-            lo2[(int64_t)rr * ldh + cc] = bf16_rne(r1 - bf16_f(l));
+            if (lo2) lo2[(int64_t)rr * ldh + cc] = bf16_rne(r1 - bf16_f(l));
         }
     }
     if (hiT) {  // uniform over the block
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void convert_kernel(const float *__restrict__ 
                 const u16 l = bf16_rne(r1);
                 hiT[(int64_t)cc * ldt + rr] = h;
                 loT[(int64_t)cc * ldt + rr] = l;
-                lo2T[(int64_t)cc * ldt + rr] = bf16_rne(r1 - bf16_f(l));
+                if (lo2T) lo2T[(int64_t)cc * ldt + rr] = bf16_rne(r1 - bf16_f(l));
             }
         }
     }
@@ -493,14 +494,15 @@ sr_status alloc_bf(sr_mlp *M, Bf &b, int64_t rows, int64_t ld, int64_t cols, int
 }
 
 // X (R x Cc) -> b.hi/lo/lo2 over Rp x Cp and b.hiT/loT/lo2T over Cp x Rp (those present)
+// third: also the lo2 pieces (read by the six-product matrix products only)
 sr_status convert(const float *X, int64_t R, int64_t Cc, int64_t ldx, int64_t Rp, int64_t Cp, const Bf &b,
-                  bool rowmajor, bool transposed, hipStream_t s)
+                  bool rowmajor, bool transposed, bool third, hipStream_t s)
 {
     dim3 grid((unsigned)((Cp + 31) / 32), (unsigned)((Rp + 31) / 32));
     hipLaunchKernelGGL(convert_kernel, grid, dim3(256), 0, s, X, (int)R, (int)Cc, ldx, (int)Rp, (int)Cp,
-                       rowmajor ? b.hi : nullptr, rowmajor ? b.lo : nullptr, rowmajor ? b.lo2 : nullptr, b.ld,
-                       transposed ? b.hiT : nullptr, transposed ? b.loT : nullptr, transposed ? b.lo2T : nullptr,
-                       b.ldT);
+                       rowmajor ? b.hi : nullptr, rowmajor ? b.lo : nullptr, rowmajor && third ? b.lo2 : nullptr,
+                       b.ld, transposed ? b.hiT : nullptr, transposed ? b.loT : nullptr,
+                       transposed && third ? b.lo2T : nullptr, b.ldT);
     MHIP(hipGetLastError());
     return SR_OK;
 }
@@ -555,10 +557,10 @@ enum { PW1 = 0, PB1, PW2, PB2, PW3, PB3, PW4, PB4, PWH };
 sr_status refresh_weights(sr_mlp *M, hipStream_t s)
 {
     const int W = M->W;
-    MSR(convert(blk(M, M->theta, PW2), W, W, W, W, W, M->w2, true, true, s));
-    MSR(convert(blk(M, M->theta, PW3), W, W, W, W, W, M->w3, true, true, s));
-    MSR(convert(blk(M, M->theta, PW4), (int64_t)kNMot * W, W, W, (int64_t)kNMot * W, W, M->w4, true, true, s));
-    MSR(convert(blk(M, M->theta, PWH), M->P, W, W, M->Pp, W, M->wh, true, true, s));
+    MSR(convert(blk(M, M->theta, PW2), W, W, W, W, W, M->w2, true, true, M->passes == 6, s));
+    MSR(convert(blk(M, M->theta, PW3), W, W, W, W, W, M->w3, true, true, M->passes == 6, s));
+    MSR(convert(blk(M, M->theta, PW4), (int64_t)kNMot * W, W, W, (int64_t)kNMot * W, W, M->w4, true, true, M->passes == 6, s));
+    MSR(convert(blk(M, M->theta, PWH), M->P, W, W, M->Pp, W, M->wh, true, true, M->passes == 6, s));
     return SR_OK;
 }
 
@@ -568,15 +570,15 @@ sr_status forward(sr_mlp *M, int B, const int64_t *idx, const double *g, const d
     hipLaunchKernelGGL(l1_forward_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, B, Bp, idx, g, M->gmid,
                        M->ghalf, blk(M, M->theta, PW1), blk(M, M->theta, PB1), W, M->gt, M->h1);
     MHIP(hipGetLastError());
-    MSR(convert(M->h1, Bp, W, W, Bp, W, M->bh1, true, true, s));
+    MSR(convert(M->h1, Bp, W, W, Bp, W, M->bh1, true, true, M->passes == 6, s));
     MSR(gemm(M, rows_of(M->bh1), rows_of(M->w2), Bp, W, W, M->h2, W, blk(M, M->theta, PB2), 1, 1, s));
-    MSR(convert(M->h2, Bp, W, W, Bp, W, M->bh2, true, true, s));
+    MSR(convert(M->h2, Bp, W, W, Bp, W, M->bh2, true, true, M->passes == 6, s));
     MSR(gemm(M, rows_of(M->bh2), rows_of(M->w3), Bp, W, W, M->h3, W, blk(M, M->theta, PB3), 1, 1, s));
-    MSR(convert(M->h3, Bp, W, W, Bp, W, M->bh3, true, true, s));
+    MSR(convert(M->h3, Bp, W, W, Bp, W, M->bh3, true, true, M->passes == 6, s));
     MSR(gemm(M, rows_of(M->bh3), rows_of(M->w4), Bp, K4, W, M->a4, K4, blk(M, M->theta, PB4), 0, 1, s));
     hipLaunchKernelGGL(contract_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, B, Bp, idx, mot, M->a4, W, M->z);
     MHIP(hipGetLastError());
-    MSR(convert(M->z, Bp, W, W, Bp, W, M->bz, true, true, s));
+    MSR(convert(M->z, Bp, W, W, Bp, W, M->bz, true, true, M->passes == 6, s));
     MSR(gemm(M, rows_of(M->bz), rows_of(M->wh), Bp, (int)M->P, W, M->o, M->Pp, nullptr, 0, 1, s));
     return SR_OK;
 }
@@ -592,7 +594,7 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, M->lpart, Bp * kLossCols,
                        1.0 / ((double)B * (double)P), M->lval);
     MHIP(hipGetLastError());
-    MSR(convert(M->dout, Bp, P, Pp, Bp, Pp, M->bdout, true, true, s));
+    MSR(convert(M->dout, Bp, P, Pp, Bp, Pp, M->bdout, true, true, M->passes == 6, s));
     // head: dWh = dout^T z, dz = dout Wh
     MSR(gemm(M, cols_of(M->bdout), cols_of(M->bz), (int)P, W, Bp, blk(M, M->grad, PWH), W, nullptr, 0, 1, s));
     const int S = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, Pp / 512));
@@ -600,7 +602,7 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
     hipLaunchKernelGGL(contract_back_kernel, dim3(nblk((int64_t)Bp * K4)), dim3(256), 0, s, B, Bp, idx, mot, M->dz, W,
                        M->da4);
     MHIP(hipGetLastError());
-    MSR(convert(M->da4, Bp, K4, K4, Bp, K4, M->bda4, true, true, s));
+    MSR(convert(M->da4, Bp, K4, K4, Bp, K4, M->bda4, true, true, M->passes == 6, s));
     // layer 4
     MSR(gemm(M, cols_of(M->bda4), cols_of(M->bh3), K4, W, Bp, blk(M, M->grad, PW4), W, nullptr, 0, 1, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(nblk(K4)), dim3(256), 0, s, B, K4, M->da4, (int64_t)K4, blk(M, M->grad, PB4));
@@ -610,7 +612,7 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
     hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, (int64_t)Bp * W, M->dh, M->h3,
                        M->d3);
     MHIP(hipGetLastError());
-    MSR(convert(M->d3, Bp, W, W, Bp, W, M->bd3, true, true, s));
+    MSR(convert(M->d3, Bp, W, W, Bp, W, M->bd3, true, true, M->passes == 6, s));
     MSR(gemm(M, cols_of(M->bd3), cols_of(M->bh2), W, W, Bp, blk(M, M->grad, PW3), W, nullptr, 0, 1, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(nblk(W)), dim3(256), 0, s, B, W, M->d3, (int64_t)W, blk(M, M->grad, PB3));
     MHIP(hipGetLastError());
@@ -619,7 +621,7 @@ sr_status backward(sr_mlp *M, int B, const int64_t *idx, const double *mot, cons
     hipLaunchKernelGGL(tanh_back_kernel, dim3(nblk((int64_t)Bp * W)), dim3(256), 0, s, (int64_t)Bp * W, M->dh, M->h2,
                        M->d2);
     MHIP(hipGetLastError());
-    MSR(convert(M->d2, Bp, W, W, Bp, W, M->bd2, true, true, s));
+    MSR(convert(M->d2, Bp, W, W, Bp, W, M->bd2, true, true, M->passes == 6, s));
     MSR(gemm(M, cols_of(M->bd2), cols_of(M->bh1), W, W, Bp, blk(M, M->grad, PW2), W, nullptr, 0, 1, s));
     hipLaunchKernelGGL(colsum_kernel, dim3(nblk(W)), dim3(256), 0, s, B, W, M->d2, (int64_t)W, blk(M, M->grad, PB2));
     MHIP(hipGetLastError());
@@ -802,9 +804,15 @@ sr_status sr_mlp_set_options(sr_mlp *M, int passes, double g_mid, double g_half)
     if (passes != 1 && passes != 3 && passes != 6) return mfail(SR_EINVAL, "sr_mlp_set_options: passes must be 1, 3 or 6");
     if (!std::isfinite(g_mid) || !(g_half > 0.0) || !std::isfinite(g_half))
         return mfail(SR_EINVAL, "sr_mlp_set_options: need finite g_mid and g_half > 0");
+    const bool redo = passes == 6 && M->passes != 6 && M->have_params;
     M->passes = passes;
     M->gmid = g_mid;
     M->ghalf = g_half;
+    if (redo) {  // the weights' lo2 pieces are written only for the six-product mode
+        DevGuard g(M->device);
+        MSR(refresh_weights(M, nullptr));
+        MHIP(hipStreamSynchronize(nullptr));
+    }
     return SR_OK;
 }
 
@@ -1001,8 +1009,8 @@ sr_status sr_mlp_gemm_test(int device, int passes, int M, int N, int K, const fl
     sr_status st = T.alloc(&T.part, (int64_t)T.Bpm * T.W * kMaxSplit) == hipSuccess ? SR_OK : SR_ENOMEM;
     if (st == SR_OK) st = alloc_bf(&T, a, M, Kp, 0, 0, s);
     if (st == SR_OK) st = alloc_bf(&T, b, N, Kp, 0, 0, s);
-    if (st == SR_OK) st = convert(A, M, K, K, M, Kp, a, true, false, s);
-    if (st == SR_OK) st = convert(Bm, N, K, K, N, Kp, b, true, false, s);
+    if (st == SR_OK) st = convert(A, M, K, K, M, Kp, a, true, false, passes == 6, s);
+    if (st == SR_OK) st = convert(Bm, N, K, K, N, Kp, b, true, false, passes == 6, s);
     if (st == SR_OK) st = gemm(&T, rows_of(a), rows_of(b), M, N, Kp, C, N, nullptr, 0, 1, s);
     (void)hipStreamSynchronize(s);
     for (void *p : T.allocs) (void)hipFree(p);

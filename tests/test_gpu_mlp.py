@@ -250,3 +250,19 @@ def test_real_head_shape_matches_oracle(P):
     print(f"real shape adam step: {d:.2e}", flush=True)
     assert d <= 1e-3 * lr + 1e-6
     net.close()
+
+
+def test_switch_to_six_products_after_set_params(P):
+    """The weights' third BF16 pieces are written only in the six-product mode: switching to it after
+    the parameters are set must rebuild them (same outputs as a network made in that mode)."""
+    width, nout, batch = 64, 301, 7
+    net_a, p, g, m, _ = setup_net(P, width, nout, batch, 6)
+    net_b, _, _, _, _ = setup_net(P, width, nout, batch, 3)
+    net_b.set_options(passes=6, g_mid=GMID, g_half=GHALF)
+    oa = net_a.forward(to_dev(g), to_dev(m)).cpu().numpy()
+    ob = net_b.forward(to_dev(g), to_dev(m)).cpu().numpy()
+    assert np.array_equal(oa, ob)
+    ref = omlp.forward(p, g, m, GMID, GHALF)[0]
+    assert np.abs(ob - ref).max() / np.abs(ref).max() <= 2e-6
+    net_a.close()
+    net_b.close()

@@ -61,5 +61,5 @@ def test_warm_start_saves_iterations():
         fine.close()
     mean = {k: float(np.mean(v)) for k, v in its_by.items()}
     print(f"mean iterations: {mean}; zero / net = {mean['zero'] / mean['net']:.2f}", flush=True)
-    assert mean["net"] <= 0.7 * mean["zero"]
+    assert mean["net"] <= 0.56 * mean["zero"]  # measured 43.5 against 83.25 (1.91x)
     net.close()
