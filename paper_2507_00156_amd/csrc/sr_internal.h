@@ -132,9 +132,11 @@ struct DevParams {
 // table holds, on kTabIntervals equal intervals of x in [0, X] (X: the near radius over h, slightly
 // widened), the degree-kTabDegree interpolants in the local variable s in [-1/2, 1/2] of
 //   g1 = S1 / x,  g2 = S2 / x^3,  g3 = S3 / x^5
-// (finite and smooth at x = 0; (S2 - S3) / x^3 = g2 - x^2 g3).  Layout: coefficient k of function f on
-// interval i at tab[(f * kTabCoef + k) * kTabIntervals + i], so that the lanes of a wavefront, which
-// read the same coefficient of different intervals, hit different LDS banks.  S1/r = g1/h and so on.
+// (finite and smooth at x = 0; (S2 - S3) / x^3 = g2 - x^2 g3).  Layout: coefficients 2j and 2j + 1 of
+// function f on interval i side by side at tab[((f * kTabCoef / 2 + j) * kTabIntervals + i) * 2], so
+// that a lane reads a function's coefficients with kTabCoef / 2 16-byte LDS reads and the lanes of a
+// wavefront, which read the same pair of different intervals, hit different LDS banks.  S1/r = g1/h
+// and so on.
 constexpr int kTabIntervals = 160, kTabDegree = 7, kTabCoef = kTabDegree + 1, kTabFuncs = 3;
 constexpr int kTabDoubles = kTabIntervals * kTabFuncs * kTabCoef;
 // Builds the table for the sorted smoothing ratios rho[3], the cut-off and the range X; returns false

@@ -546,7 +546,8 @@ __device__ __forceinline__ void near_pair(const SrcRec<double> &s, const TgtV &T
 }
 
 // One near pair of a target on the surface (b = 0) in the combined mode, from the smoothing table
-// (NearTable: S1/r, S2/r^3 and S3/r^5 as polynomials on 160 intervals of r / h, held in LDS;
+// (NearTable: S1/r, S2/r^3 and S3/r^5 as polynomials on 160 intervals of r / h, held in LDS and read
+// as coefficient pairs, 12 16-byte reads per pair;
 // (S2 - S3)/r^3 = S2/r^3 - r^2 S3/r^5).  No closed forms, no exponential and no series: the table is
 // smooth through r = 0 (the target's own point adds g S1/r at its limit), so every pair takes this one
 // path.  r = r2 / sqrt(r2) from the hardware estimate and one Newton step (relative error ~4e-15);
@@ -563,12 +564,19 @@ __device__ __forceinline__ void tab_pair(const SrcRec<double> &s, const TgtV &T,
     const double u = r * p.tab_scale;
     const int i = min((int)u, kTabIntervals - 1);
     const double sv = u - (double)i - 0.5;
-    const double *c = tabs + i;
+    const double2 *c2 = reinterpret_cast<const double2 *>(tabs) + i;
     auto horner = [&](int f) {
-        const double *q = c + f * kTabCoef * kTabIntervals;
-        double v = q[kTabDegree * kTabIntervals];
+        const double2 *q = c2 + f * (kTabCoef / 2) * kTabIntervals;
+        double2 pr[kTabCoef / 2];
 #pragma unroll
-        for (int k = kTabDegree - 1; k >= 0; --k) v = __builtin_fma(v, sv, q[k * kTabIntervals]);
+        for (int k = 0; k < kTabCoef / 2; ++k) pr[k] = q[k * kTabIntervals];
+        double v = pr[kTabCoef / 2 - 1].y;
+        v = __builtin_fma(v, sv, pr[kTabCoef / 2 - 1].x);
+#pragma unroll
+        for (int k = kTabCoef / 2 - 2; k >= 0; --k) {
+            v = __builtin_fma(v, sv, pr[k].y);
+            v = __builtin_fma(v, sv, pr[k].x);
+        }
         return v;
     };
     const PairGeo G = pair_geo<SL, DL>(s, T, dx, dy, dz);
@@ -1145,7 +1153,7 @@ bool build_near_table(const double rho_d[3], double cutoff, double X, std::vecto
                 long double acc = F[f][r];
                 for (int e = r + 1; e < kTabCoef; ++e) acc -= V[r][e] * F[f][e];
                 F[f][r] = acc / V[r][r];
-                t[((size_t)f * kTabCoef + r) * kTabIntervals + i] = (double)F[f][r];
+                t[(((size_t)f * (kTabCoef / 2) + r / 2) * kTabIntervals + i) * 2 + (r & 1)] = (double)F[f][r];
             }
     }
     // check: the double-precision Horner evaluation the kernel performs against long double, at 17
@@ -1157,9 +1165,9 @@ bool build_near_table(const double rho_d[3], double cutoff, double X, std::vecto
             long double g[kTabFuncs];
             table_functions_ld(dx * (i + 0.5L + sv), rho, w, cutoff, g);
             for (int f = 0; f < kTabFuncs; ++f) {
-                const double *c = &t[(size_t)f * kTabCoef * kTabIntervals + i];
-                double v = c[kTabDegree * kTabIntervals];
-                for (int e = kTabDegree - 1; e >= 0; --e) v = std::fma(v, sv, c[e * kTabIntervals]);
+                auto coef = [&](int e) { return t[(((size_t)f * (kTabCoef / 2) + e / 2) * kTabIntervals + i) * 2 + (e & 1)]; };
+                double v = coef(kTabDegree);
+                for (int e = kTabDegree - 1; e >= 0; --e) v = std::fma(v, sv, coef(e));
                 err = std::max(err, fabsl((long double)v - g[f]) / gmax[f]);
             }
         }
