@@ -444,10 +444,12 @@ def save_model(path, net: WarmStartNet, pod: PodDecoder, gaps, motions, T, meta:
     import json
     import os
 
+    import torch
+
     os.makedirs(path, exist_ok=True)
     np.save(os.path.join(path, "params.npy"), net.get_params())
     np.save(os.path.join(path, "scale.npy"), net.output_scale().cpu().numpy())
-    np.save(os.path.join(path, "pod_v.npy"), pod.V.to(dtype=__import__("torch").float32).cpu().numpy())
+    np.save(os.path.join(path, "pod_v.npy"), pod.V.to(dtype=torch.float32).cpu().numpy())
     np.save(os.path.join(path, "coeffs.npy"), T.cpu().numpy())
     np.save(os.path.join(path, "gaps.npy"), np.asarray(gaps, float))
     np.save(os.path.join(path, "motions.npy"), np.asarray(motions, float))
