@@ -86,19 +86,25 @@ def test_deterministic(P, small):
     np.testing.assert_array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_c2_full_size_sampled(P, precision):
-    # the benchmark workload (ellipsoid 1, 0.8, 0.6; h = 1/64; N = 42342, M = 62342), evaluated in
-    # full on the GPU; the oracle recomputes 240 sampled targets one by one
+@pytest.fixture(scope="module")
+def c2_sample():
+    # the benchmark workload (ellipsoid 1, 0.8, 0.6; h = 1/64; N = 42342, M = 62342): 1000 surface and
+    # 1000 near targets sampled, plus the first and last of each kind; the oracle recomputes them one by one
     cfg = workload.build_config("c2")
     t = cfg["targets"]
     n = cfg["surf"].n
     rng = np.random.default_rng(42)
-    idx = np.concatenate([rng.choice(n, 120, replace=False), n + rng.choice(t.m - n, 120, replace=False),
+    idx = np.concatenate([rng.choice(n, 1000, replace=False), n + rng.choice(t.m - n, 1000, replace=False),
                           [0, n - 1, n, t.m - 1]])
+    return cfg, idx, oracle.sl_cfg(cfg, idx), oracle.dl_cfg(cfg, idx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_full_size_sampled(P, c2_sample, precision):
+    """Evaluated in full on the GPU, in the benchmark's launch configuration; compared on 2004 sampled
+    targets."""
+    cfg, idx, u, v = c2_sample
     gu, gv = gpu_eval(cfg, 3, precision)
-    u = oracle.sl_cfg(cfg, idx)
-    v = oracle.dl_cfg(cfg, idx)
     e1, e2 = rel_err(gu[idx], u), rel_err(gv[idx], v)
     print(f"c2 prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
     assert e1 <= TOL[precision] and e2 <= TOL[precision]
