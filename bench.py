@@ -71,7 +71,7 @@ FAR_TRAFFIC = {"bytes": {"fp64": 1.074e8, "mixed": 9.786e7},
                "sources": {"paper_2507_00156_amd/csrc/sr_far.hip":
                            "5f769e32b82e18b25269dc80e51b0771830f5c67136ac01102e174866ce8632a",
                            "paper_2507_00156_amd/csrc/sr_internal.h":
-                           "9a35a236872a00f31b1a413c828277e4ed3c04b8bc312c59041f64a1f4b0491a"}}
+                           "a38c60466ccaff6e83f185cb5e6994014831aad5b9554f5b1a89adbe6fde6f22"}}
 
 
 def far_traffic(precision):

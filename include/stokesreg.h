@@ -116,7 +116,9 @@ sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
  * (Stokes_DL1), (extrap_eqn); y = x0 + b n0 as defined there).
  *   layers      SR_SL, SR_DL or SR_SL|SR_DL (both in one pass, sharing the pair geometry); | SR_HOST
  *               for host arrays (the call then synchronizes `stream`).
- *   m           0 <= m <= sr_max_targets() (2^28); SR_EINVAL otherwise.
+ *   m           0 <= m <= sr_max_targets() (2^28); SR_EINVAL otherwise.  Evaluated in chunks of at
+ *               most 2^20 targets, one after the other, so that the context's work space (768 bytes per
+ *               target of a chunk for the far-field partial sums) stays bounded.
  *   y (m,3)     target points.
  *   x0 (m,3)    closest point on the surface to each target;  n0 (m,3) the outward unit normal there;
  *   b (m)       signed distance, y = x0 + b n0 (b > 0 outside, b < 0 inside, b == 0 on the surface).
@@ -183,8 +185,8 @@ sr_status sr_eval_noalloc(sr_ctx *c, int layers, int64_t m, const double *y, con
 /* Per-phase timing.  While profiling is on, every sr_eval runs its phases one after the other on
  * its stream (not concurrently) and records HIP events around each: SR_PHASE_FAR (the far-field
  * sum) and SR_PHASE_NEAR (near regularized sums plus extrapolation).  sr_get_profile waits for the recorded events, writes the accumulated
- * milliseconds per phase to ms[0..SR_NPHASES-1] and the number of recorded evaluations to *evals,
- * and clears the record. */
+ * milliseconds per phase to ms[0..SR_NPHASES-1] and the number of recorded evaluations to *evals
+ * (an evaluation of more than 2^20 targets counts once per chunk), and clears the record. */
 enum { SR_PHASE_FAR = 0, SR_PHASE_NEAR = 1, SR_NPHASES = 2 };
 sr_status sr_set_profiling(sr_ctx *c, int on);
 sr_status sr_get_profile(sr_ctx *c, double *ms, int64_t *evals);

@@ -430,8 +430,8 @@ sr_status sr_create(sr_ctx **out, int device)
             return fail(SR_EHIP, "sr_create: cannot resolve the static scratch array: %s", hipGetErrorString(e));
         }
         // the target-consistency report, cleared
-        e = hipMalloc((void **)&c->flag, sizeof(NearFlag));
-        if (e == hipSuccess) e = launch_flag_clear(c->flag, c->side);
+        e = hipMalloc((void **)&c->flag, kFlagSlots * sizeof(NearFlag));
+        if (e == hipSuccess) e = launch_flag_clear(c->flag, kFlagSlots, c->side);
         if (e == hipSuccess) e = hipStreamSynchronize(c->side);
         if (e != hipSuccess) {
             delete c;
@@ -555,10 +555,12 @@ sr_status sr_set_density(sr_ctx *c, int layer, const double *dens, void *stream)
 
 }  // extern "C"
 
-// The evaluation on device arrays (sr::eval_on_device in sr_internal.h).
-sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, const double *y, const double *x0,
-                             const double *n0, const double *b, const double *f0, const double *q0, double *u,
-                             double *v, double *u_delta, double *v_delta, hipStream_t s, double *ext_part)
+namespace {
+
+// One chunk of at most kTargetChunk targets of eval_on_device; its consistency reports go to *flag.
+sr_status eval_chunk(const char *fn, sr_ctx *c, int layers, int64_t m, const double *y, const double *x0,
+                     const double *n0, const double *b, const double *f0, const double *q0, double *u, double *v,
+                     double *u_delta, double *v_delta, hipStream_t s, double *ext_part, NearFlag *flag)
 {
     sr_status st;
     const bool noalloc = ext_part != nullptr;
@@ -731,7 +733,7 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
         hipError_t e0 = hipStreamWaitEvent(c->side, c->ev_fork, 0);
         hipError_t e1 = e0 == hipSuccess
                             ? launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p,
-                                                   c->cell_start.p, c->grid, a, dp, nullptr, 0, c->flag, c->side)
+                                                   c->cell_start.p, c->grid, a, dp, nullptr, 0, flag, c->side)
                             : e0;
         hipError_t e2 = hipEventRecord(c->ev_join, c->side);
         hipError_t e3 = hipStreamWaitEvent(s, c->ev_join, 0);
@@ -742,8 +744,29 @@ sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, c
     }
     if (profile && (st = record_event(c, s)) != SR_OK) return st;
     SR_HIP(launch_near_finalize(c->prm.precision, layers, c->rec64.p, c->pos64.p, c->pos32.p, c->cell_start.p,
-                                c->grid, a, dp, part, nparts, c->flag, s));
+                                c->grid, a, dp, part, nparts, flag, s));
     if (profile && (st = record_event(c, s)) != SR_OK) return st;
+    return SR_OK;
+}
+
+}  // namespace
+
+// The evaluation on device arrays (sr::eval_on_device in sr_internal.h): chunks of at most kTargetChunk
+// targets one after the other, so that the far-field partial sums (768 bytes per target) and the target
+// order stay bounded whatever m is; chunk i reports to the context's flag slot i.
+sr_status sr::eval_on_device(const char *fn, sr_ctx *c, int layers, int64_t m, const double *y, const double *x0,
+                             const double *n0, const double *b, const double *f0, const double *q0, double *u,
+                             double *v, double *u_delta, double *v_delta, hipStream_t s, double *ext_part)
+{
+    auto at = [](auto *p, int64_t k) { return p ? p + k : p; };
+    for (int64_t c0 = 0, i = 0; c0 < m; c0 += kTargetChunk, ++i) {
+        const int64_t mc = std::min<int64_t>(kTargetChunk, m - c0);
+        const sr_status st =
+            eval_chunk(fn, c, layers, mc, at(y, 3 * c0), at(x0, 3 * c0), at(n0, 3 * c0), at(b, c0), at(f0, 3 * c0),
+                       at(q0, 3 * c0), at(u, 3 * c0), at(v, 3 * c0), at(u_delta, 9 * c0), at(v_delta, 9 * c0), s,
+                       ext_part, c->flag + i);
+        if (st != SR_OK) return st;
+    }
     return SR_OK;
 }
 
@@ -877,17 +900,21 @@ sr_status sr_eval_far(sr_ctx *c, int layers, int64_t m, const double *y, double 
         {(layers & SR_DL) ? v : nullptr, &dv, m3, false},
     };
     if (host && (st = stage_in("sr_eval_far", c, arr, s)) != SR_OK) return st;
-    EvalArgs a{};
-    a.layers = layers;
-    a.m = m;
-    a.y = dy;
-    a.u = du;
-    a.v = dv;
-    for (int d = 0; d < 3; ++d) a.org[d] = c->prm.precision == SR_MIXED ? c->org[d] : 0.0;
-    SR_HIP(c->part.reserve((size_t)kFarSplits * 6 * (size_t)m));
-    SR_HIP(launch_far_plain(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, c->grid_rnear, c->flag,
-                            c->part.p, s));
-    SR_HIP(launch_far_add(layers, c->part.p, kFarSplits, a, true, s));
+    // in chunks of at most kTargetChunk targets, as sr_eval
+    for (int64_t c0 = 0, i = 0; c0 < m; c0 += kTargetChunk, ++i) {
+        const int64_t mc = std::min<int64_t>(kTargetChunk, m - c0);
+        EvalArgs a{};
+        a.layers = layers;
+        a.m = mc;
+        a.y = dy + 3 * c0;
+        a.u = du ? du + 3 * c0 : nullptr;
+        a.v = dv ? dv + 3 * c0 : nullptr;
+        for (int d = 0; d < 3; ++d) a.org[d] = c->prm.precision == SR_MIXED ? c->org[d] : 0.0;
+        SR_HIP(c->part.reserve((size_t)kFarSplits * 6 * (size_t)mc));
+        SR_HIP(launch_far_plain(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, c->grid_rnear,
+                                c->flag + i, c->part.p, s));
+        SR_HIP(launch_far_add(layers, c->part.p, kFarSplits, a, true, s));
+    }
     return host ? stage_out(c, arr, s) : SR_OK;
 }
 
@@ -898,12 +925,19 @@ sr_status sr_check(sr_ctx *c, void *stream)
     DeviceGuard g(c->device);
     if (!g.ok) return fail(SR_ENODEV, "sr_check: cannot select device %d", c->device);
     hipStream_t s = (hipStream_t)stream;
-    NearFlag hf{};
     SR_HIP(hipStreamSynchronize(s));
     SR_HIP(hipStreamSynchronize(c->side));
-    SR_HIP(hipMemcpy(&hf, c->flag, sizeof hf, hipMemcpyDeviceToHost));
+    std::vector<NearFlag> slots(kFlagSlots);
+    SR_HIP(hipMemcpy(slots.data(), c->flag, kFlagSlots * sizeof(NearFlag), hipMemcpyDeviceToHost));
+    // slot i holds the reports of target chunk i: its first index is relative to the chunk
+    NearFlag hf{0u, 0u, ~0ull};
+    for (int i = 0; i < kFlagSlots; ++i)
+        if (slots[i].bits != 0u) {
+            hf.bits |= slots[i].bits;
+            hf.first = std::min<unsigned long long>(hf.first, (unsigned long long)i * kTargetChunk + slots[i].first);
+        }
     if (hf.bits == 0) return SR_OK;
-    SR_HIP(launch_flag_clear(c->flag, s));
+    SR_HIP(launch_flag_clear(c->flag, kFlagSlots, s));
     SR_HIP(hipStreamSynchronize(s));
     if (hf.bits & kFlagFarTarget)
         return fail(SR_ENEAR, "sr_check: target %llu of sr_eval_far lies within the near radius of a source: it needs "

@@ -84,6 +84,10 @@ struct NearFlag {
 // Largest number of targets of one evaluation: 3 * m stays below 2^31, so the kernels' 32-bit
 // target indices (3 t + component) cannot overflow.
 constexpr int64_t kMaxTargets = int64_t(1) << 28;
+// An evaluation runs in chunks of at most this many targets (its far-field partial sums, 768 bytes per
+// target, and its target order are sized for one chunk); chunk i reports to NearFlag slot i.
+constexpr int64_t kTargetChunk = int64_t(1) << 20;
+constexpr int kFlagSlots = (int)(kMaxTargets / kTargetChunk);
 
 struct EvalArgs {
     int layers;          // SR_SL | SR_DL bits
@@ -166,8 +170,8 @@ hipError_t launch_near_finalize(int precision, int layers, const SrcRec<double> 
 // u += far / (8 pi), v += -6 far / (8 pi) for outputs written by launch_near_finalize with nparts = 0;
 // with store, u = far / (8 pi), v = -6 far / (8 pi) (the plain sums of sr_eval_far)
 hipError_t launch_far_add(int layers, const double *part, int nparts, const EvalArgs &a, bool store, hipStream_t s);
-// *flag = no report (bits 0, first = all ones)
-hipError_t launch_flag_clear(NearFlag *flag, hipStream_t s);
+// flag[0 .. n) = no report (bits 0, first = all ones)
+hipError_t launch_flag_clear(NearFlag *flag, int n, hipStream_t s);
 
 // ---- the evaluation shared by the C entry points (sr_api.hip) ----
 // Checks layers (SR_SL, SR_DL or both), 0 <= m <= max_m, then the context's state; sets the thread's

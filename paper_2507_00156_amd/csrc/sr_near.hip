@@ -985,11 +985,11 @@ __global__ __launch_bounds__(kBlock) void far_add_kernel(const double *__restric
     *o = STORE ? val : *o + val;
 }
 
-__global__ void flag_clear_kernel(NearFlag *flag)
+__global__ void flag_clear_kernel(NearFlag *flag, int n)
 {
-    if (threadIdx.x == 0) {
-        flag->bits = 0u;
-        flag->first = ~0ull;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+        flag[i].bits = 0u;
+        flag[i].first = ~0ull;
     }
 }
 
@@ -1018,9 +1018,9 @@ hipError_t launch_far_add(int layers, const double *part, int nparts, const Eval
     return hipGetLastError();
 }
 
-hipError_t launch_flag_clear(NearFlag *flag, hipStream_t s)
+hipError_t launch_flag_clear(NearFlag *flag, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(flag_clear_kernel, dim3(1), dim3(kWave), 0, s, flag);
+    hipLaunchKernelGGL(flag_clear_kernel, dim3(1), dim3(kBlock), 0, s, flag, n);
     return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
 - SR_ENEAR (sr_check) for a far-kind target inside the near radius, and for an sr_eval target whose
   stated |b| selects the far rule while a source is closer (paper section 3.3: the regularization
   acts within cutoff * delta of a source), and no report for honest targets;
-- the host-pointer mode (SR_HOST) gives the device mode's results bit for bit.
+- the host-pointer mode (SR_HOST) gives the device mode's results bit for bit;
+- an evaluation of more than 2^20 targets (run in chunks) equals its targets' single evaluations.
 """
 import numpy as np
 import pytest
@@ -130,4 +131,42 @@ def test_host_pointer_mode_equals_device_mode(precision):
     assert np.array_equal(uh, u.cpu().numpy()) and np.array_equal(vh, v.cpu().numpy())
     _, vd = ev.eval_host(P.SR_DL, t.y, t.x0, t.n0, t.b, None, cfg["q0"])
     assert np.array_equal(vd, v.cpu().numpy())
+    ev.close()
+
+
+def test_evaluation_in_chunks_equals_one_chunk():
+    """More than 2^20 targets are evaluated in chunks of 2^20 one after the other: every target's
+    result equals (bit for bit) that of an evaluation of its own copy alone, and a report of the second
+    chunk names the target's index in the whole call."""
+    import torch
+
+    import paper_2507_00156_amd as P
+
+    cfg = workload.build_config("small")
+    t = cfg["targets"]
+    reps = (1 << 20) // t.m + 2  # more than 2^20 targets in all
+    m = reps * t.m
+    ev = _setup(cfg, 1)
+    args1 = [to_dev(a) for a in (t.y, t.x0, t.n0, t.b, cfg["f0"], cfg["q0"])]
+    u1, v1 = ev.eval(P.SR_SL | P.SR_DL, *args1)
+    torch.cuda.synchronize()
+    argsn = [a.repeat((reps, 1)) if a.dim() == 2 else a.repeat(reps) for a in args1]
+    un, vn = ev.eval(P.SR_SL | P.SR_DL, *argsn)
+    torch.cuda.synchronize()
+    ev.check()
+    assert un.shape[0] == m > (1 << 20)
+    assert torch.equal(un, u1.repeat((reps, 1))) and torch.equal(vn, v1.repeat((reps, 1)))
+    # a copy, in the second chunk, of a surface target (its own point is a source) whose b claims the
+    # far rule
+    h, rho = cfg["h"], cfg["rho"]
+    on = int(np.nonzero(t.b == 0.0)[0][0])
+    k = ((1 << 20) // t.m + 1) * t.m + on
+    assert k > (1 << 20)
+    bw = argsn[3].clone()
+    bw[k] = 1.5 * 6.0 * max(rho) * h
+    ev.eval(P.SR_SL | P.SR_DL, argsn[0], argsn[1], argsn[2], bw, argsn[4], argsn[5])
+    with pytest.raises(P.SrError) as ei:
+        ev.check()
+    assert ei.value.status == P.SR_ENEAR and f"target {k} " in str(ei.value)
+    ev.check()
     ev.close()
