@@ -161,6 +161,30 @@ sr_status sr_check(sr_ctx *c, void *stream);
 /* Largest number of targets (and of surface points) the evaluation calls accept: 2^28. */
 int64_t sr_max_targets(void);
 
+/* The smoothing table that sr_eval's near-field phase uses for targets on the surface (b = 0), built
+ * on the host for inspection.  At b = 0 the extrapolation weights w_j of the three runs (eq.
+ * (extrap_eqn) with I0(0) = 1/sqrt(pi), I2(0) = 1/(3 sqrt(pi))) are the same for every target, so the
+ * combined smoothing factors S_k(x) = sum_j w_j s_k(x / rho_j) (eqs. (s1)-(s3); s_k = 1 beyond the
+ * cut-off, section 3.2) are fixed functions of x = r/h.  The table holds
+ *   g1 = S1 / x,  g2 = S2 / x^3,  g3 = S3 / x^5
+ * on SR_NEAR_TABLE_INTERVALS equal intervals of [0, xmax], each as a polynomial of degree
+ * SR_NEAR_TABLE_DEGREE in s in [-1/2, 1/2] (x = (i + 1/2 + s) xmax / SR_NEAR_TABLE_INTERVALS on
+ * interval i).  Coefficient e of function f (0..2) on interval i is
+ *   tab[((f * (D + 1) / 2 + e / 2) * NI + i) * 2 + e % 2]      (D the degree, NI the interval count).
+ *   rho     the three delta/h ratios, positive and distinct (any order).
+ *   cutoff  the cut-off of the smoothing functions (> 0).   xmax  > 0.
+ *   tab     host array of n >= SR_NEAR_TABLE_DOUBLES doubles, written on success.
+ *   maxerr  if not NULL, receives the largest error of the double-precision Horner evaluation of
+ *           the table against long-double evaluations, at 17 points per interval, relative to the
+ *           function's largest value.
+ * SR_EINVAL for NULL rho or tab, n too small, or a parameter out of range; SR_ENOCONV if the checked
+ * error exceeds 5e-14 (tab is then left unchanged; sr_eval uses the closed forms for such
+ * parameters).  Host only: needs no GPU. */
+#define SR_NEAR_TABLE_INTERVALS 160
+#define SR_NEAR_TABLE_DEGREE 7
+#define SR_NEAR_TABLE_DOUBLES (SR_NEAR_TABLE_INTERVALS * 3 * (SR_NEAR_TABLE_DEGREE + 1))
+sr_status sr_near_table(const double rho[3], double cutoff, double xmax, double *tab, int64_t n, double *maxerr);
+
 /* sr_eval for callers that cannot allocate device memory: code under HIP graph capture, serving loops
  * that must not call hipMalloc, harnesses that forbid it.  The same evaluation as sr_eval (same
  * kernels, same results) on DEVICE arrays, with no per-delta outputs and no SR_HOST; the far-field

@@ -21,7 +21,7 @@ _NAMES = {0: "SR_OK", -1: "SR_EINVAL", -2: "SR_ENOMEM", -3: "SR_ENODEV", -4: "SR
 
 # every symbol the header declares; the CPU test-suite checks that the library exports each one
 EXPORTS = ("sr_default_params", "sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density",
-           "sr_eval", "sr_eval_far", "sr_eval_noalloc", "sr_check", "sr_max_targets", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+           "sr_eval", "sr_eval_far", "sr_eval_noalloc", "sr_check", "sr_max_targets", "sr_near_table", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
            "sr_rigid_set_params", "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve",
            "sr_rigid_solve_refined", "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity", "sr_rigid_last_error", "sr_prolong_create",
            "sr_prolong_apply", "sr_prolong_destroy", "sr_mlp_num_params", "sr_mlp_create", "sr_mlp_destroy",
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_check.argtypes = [vp, vp]
     L.sr_max_targets.argtypes = []
     L.sr_max_targets.restype = i64
+    L.sr_near_table.argtypes = [d, C.c_double, C.c_double, d, i64, d]
     L.sr_set_profiling.argtypes = [vp, C.c_int]
     L.sr_get_profile.argtypes = [vp, d, C.POINTER(C.c_int64)]
     L.sr_tree_work.argtypes = [vp, i64, vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
@@ -122,7 +123,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.sr_version.argtypes = []
     L.sr_version.restype = C.c_char_p
     for fn in ("sr_create", "sr_destroy", "sr_set_params", "sr_set_surface", "sr_set_density", "sr_eval",
-               "sr_eval_far", "sr_eval_noalloc", "sr_check", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
+               "sr_eval_far", "sr_eval_noalloc", "sr_check", "sr_near_table", "sr_set_profiling", "sr_get_profile", "sr_tree_work", "sr_rigid_create", "sr_rigid_destroy",
                "sr_rigid_set_params",
                "sr_rigid_set_spheres", "sr_rigid_rhs", "sr_rigid_matvec", "sr_rigid_solve", "sr_rigid_solve_refined",
                "sr_rigid_set_operator", "sr_rigid_single_layer", "sr_rigid_velocity"):
@@ -274,6 +275,25 @@ def sr_check(ctx, stream=None) -> None:
 
 def sr_max_targets() -> int:
     return int(load_library().sr_max_targets())
+
+
+SR_NEAR_TABLE_INTERVALS, SR_NEAR_TABLE_DEGREE = 160, 7
+SR_NEAR_TABLE_DOUBLES = SR_NEAR_TABLE_INTERVALS * 3 * (SR_NEAR_TABLE_DEGREE + 1)
+
+
+def sr_near_table(rho, cutoff: float, xmax: float):
+    """The surface-target smoothing table (host only): returns (coefficients as a float64 array of
+    shape (3, (D + 1) / 2, NI, 2), the checked interpolation error).  Coefficient e of function f on
+    interval i is out[f, e // 2, i, e % 2]."""
+    import numpy as np
+
+    r = (C.c_double * 3)(*[float(v) for v in rho])
+    tab = np.zeros(SR_NEAR_TABLE_DOUBLES)
+    err = C.c_double()
+    _check("sr_near_table", load_library().sr_near_table(r, float(cutoff), float(xmax),
+                                                         tab.ctypes.data_as(C.POINTER(C.c_double)),
+                                                         SR_NEAR_TABLE_DOUBLES, C.byref(err)))
+    return tab.reshape(3, (SR_NEAR_TABLE_DEGREE + 1) // 2, SR_NEAR_TABLE_INTERVALS, 2), float(err.value)
 
 
 def sr_set_profiling(ctx, on: bool) -> None:

@@ -948,6 +948,31 @@ sr_status sr_check(sr_ctx *c, void *stream)
 
 int64_t sr_max_targets(void) { return kMaxTargets; }
 
+static_assert(SR_NEAR_TABLE_INTERVALS == kTabIntervals && SR_NEAR_TABLE_DEGREE == kTabDegree &&
+                  SR_NEAR_TABLE_DOUBLES == kTabDoubles,
+              "the table layout of the header and of the near-field kernel differ");
+
+sr_status sr_near_table(const double rho[3], double cutoff, double xmax, double *tab, int64_t n, double *maxerr)
+{
+    g_err.clear();
+    if (!rho || !tab || n < kTabDoubles)
+        return fail(SR_EINVAL, "sr_near_table: NULL argument or n < %d", kTabDoubles);
+    for (int j = 0; j < 3; ++j)
+        if (!(rho[j] > 0.0) || !std::isfinite(rho[j]))
+            return fail(SR_EINVAL, "sr_near_table: rho[%d] must be positive and finite", j);
+    if (rho[0] == rho[1] || rho[0] == rho[2] || rho[1] == rho[2])
+        return fail(SR_EINVAL, "sr_near_table: the three rho must be distinct");
+    if (!(cutoff > 0.0) || !std::isfinite(cutoff) || !(xmax > 0.0) || !std::isfinite(xmax))
+        return fail(SR_EINVAL, "sr_near_table: cutoff and xmax must be positive and finite");
+    std::vector<double> t;
+    double err = 0.0;
+    const bool ok = build_near_table(rho, cutoff, xmax, t, &err);
+    if (maxerr) *maxerr = err;
+    if (!ok) return fail(SR_ENOCONV, "sr_near_table: interpolation error %.3g exceeds 5e-14", err);
+    std::copy(t.begin(), t.end(), tab);
+    return SR_OK;
+}
+
 sr_status sr_tree_work(sr_ctx *c, int64_t m, const double *y, int64_t *proxy_pairs, int64_t *leaf_pairs,
                        int64_t *cluster_points)
 {

@@ -291,14 +291,19 @@ def test_surface_table_equals_closed_forms(P, small, precision):
 
 
 def test_surface_targets_without_table_match_oracle(P, small):
-    """With rho = 1 : 2 : 3 the smoothing table misses its accuracy check (the smallest delta is h) and
-    the surface targets take the closed forms in the combined mode; parity with the oracle."""
+    """With rho = 1 : 2 : 4 the smoothing table misses its accuracy check (the smallest delta is h, the
+    range 24 h) and the surface targets take the closed forms in the combined mode; parity with the
+    oracle."""
     cfg, _ = small
-    cfg = dict(cfg, rho=(1.0, 2.0, 3.0))
+    rho = (1.0, 2.0, 4.0)
+    with pytest.raises(P.SrError) as ei:  # the table the evaluation would build: refused
+        P.sr_near_table(rho, 6.0, 6.0 * 4.0 * (1.0 + 1e-5))
+    assert ei.value.status == -6
+    cfg = dict(cfg, rho=rho)
     u = oracle.sl_cfg(cfg)
     v = oracle.dl_cfg(cfg)
     for precision in (0, 1):
         gu, gv = gpu_eval(cfg, P.SR_SL | P.SR_DL, precision)[:2]
         e1, e2 = rel_err(gu, u), rel_err(gv, v)
-        print(f"rho 1:2:3 prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
+        print(f"rho 1:2:4 prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
         assert e1 <= TOL[precision] and e2 <= TOL[precision]
