@@ -74,7 +74,12 @@ typedef struct {
     int precision;      /* SR_FP64 or SR_MIXED                                                    */
     int far_method;     /* SR_DIRECT or SR_TREE                                                   */
     int tree_degree;    /* treecode: Chebyshev interpolation degree p (1..16)                     */
-    double tree_theta;  /* treecode: multipole acceptance parameter theta, MAC r_c / R <= theta   */
+    double tree_theta;  /* treecode: multipole acceptance parameter theta, MAC r_c / R <= theta,
+                           and the cluster's box farther than the near radius R_n = cutoff
+                           max(rho, sharp_rho if surface_sharp) h.  With SR_MIXED the box must lie
+                           farther than R_n (1 + 1e-5) + 2^-22 (2 E + R_n), E = max_d (max_i x_id
+                           - min_i x_id) / 2 (the reach of the single-precision near-pair test), so
+                           that no source of an accepted cluster is also summed as a near pair     */
     int tree_leaf;      /* treecode: maximum number of points in a leaf N0 (>= 1)                 */
     int surface_sharp;  /* 1: targets ON the surface (b == 0) use the modified smoothing functions
                            s1#, s2#, s3# of paper section 2.1 at the single delta sharp_rho h, with no

@@ -41,7 +41,7 @@ def lib():
         L.orc_dl.argtypes = [i64, d, d, d, d, i64, d, d, d, d, d, C.c_double, d, d, d, d]
         L.orc_plain.argtypes = [i64, d, d, d, d, d, i64, d, d, d]
         L.orc_tree.argtypes = [i64, d, d, d, d, d, i64, d, d, d, d, d, d, C.c_double, d, C.c_int, C.c_double, i64,
-                               d, d, d, d]
+                               C.c_double, d, d, d, d]
         L.orc_tree.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -174,8 +174,9 @@ def plain(surf_x, surf_n, surf_w, f, q, y):
 
 
 def tree(surf_x, surf_n, surf_w, f, q, y, x0, n0, b, f0, q0, h, rho, p=8, theta=0.7, leaf=2000,
-         want_delta=False):
-    """Treecode evaluation of both layers (paper section 3.4); returns (u, v[, ud, vd, nnodes])."""
+         want_delta=False, mac_rnear=None):
+    """Treecode evaluation of both layers (paper section 3.4); returns (u, v[, ud, vd, nnodes]).
+    mac_rnear: the radius the MAC requires a cluster's box to lie beyond (default: the near radius)."""
     x, nn, w, f, q = (_f64(a) for a in (surf_x, surf_n, surf_w, f, q))
     y, x0, n0, b, f0, q0 = (_f64(a) for a in (y, x0, n0, b, f0, q0))
     m = y.shape[0]
@@ -184,18 +185,19 @@ def tree(surf_x, surf_n, surf_w, f, q, y, x0, n0, b, f0, q0, h, rho, p=8, theta=
     ud = np.zeros((m, 3, 3)) if want_delta else None
     vd = np.zeros((m, 3, 3)) if want_delta else None
     nn_ = lib().orc_tree(x.shape[0], _p(x), _p(nn), _p(w), _p(f), _p(q), m, _p(y), _p(x0), _p(n0), _p(b), _p(f0),
-                         _p(q0), float(h), _p(r), int(p), float(theta), int(leaf), _p(u), _p(v),
+                         _p(q0), float(h), _p(r), int(p), float(theta), int(leaf),
+                         float(mac_rnear) if mac_rnear is not None else 0.0, _p(u), _p(v),
                          _p(ud) if ud is not None else None, _p(vd) if vd is not None else None)
     if nn_ < 0:
         raise FloatingPointError("singular extrapolation system")
     return (u, v, ud, vd, nn_) if want_delta else (u, v)
 
 
-def tree_cfg(cfg, idx=None, p=8, theta=0.7, leaf=2000, want_delta=False):
+def tree_cfg(cfg, idx=None, p=8, theta=0.7, leaf=2000, want_delta=False, mac_rnear=None):
     s, t = cfg["surf"], cfg["targets"]
     sel = slice(None) if idx is None else np.asarray(idx)
     return tree(s.x, s.normal, s.w, cfg["f"], cfg["q"], t.y[sel], t.x0[sel], t.n0[sel], t.b[sel], cfg["f0"][sel],
-                cfg["q0"][sel], cfg["h"], cfg["rho"], p, theta, leaf, want_delta)
+                cfg["q0"][sel], cfg["h"], cfg["rho"], p, theta, leaf, want_delta, mac_rnear)
 
 
 def num_threads() -> int:

@@ -581,13 +581,15 @@ typedef struct {
     const double *mw;  /* modified weights: [node][proxy][15] */
     int p;
     double theta, rnear, h, rho[3];
+    double mac_rnear; /* the MAC's near radius (>= rnear) */
 } tree_ctx;
 
 static void tree_visit(const tree_ctx *C, int id, const double *yt, const double *x0t, const double *nn, double bb,
                        double c, const double *q0t, double us[3][3], double vs[3][3])
 {
     const orc_node *nd = &C->T->nodes[id];
-    /* MAC: r_c <= theta R, and the whole box farther than the near radius */
+    /* MAC: r_c <= theta R, and the whole box farther than the near radius (mac_rnear: a caller whose
+     * near-pair test rounds may widen it, so that no source of an accepted cluster is a near pair) */
     double rc2 = 0.0, R2 = 0.0, g2 = 0.0;
     for (int d = 0; d < 3; ++d) {
         double e = nd->hi[d] - nd->lo[d];
@@ -597,7 +599,7 @@ static void tree_visit(const tree_ctx *C, int id, const double *yt, const double
         double gap = nd->lo[d] - yt[d] > 0.0 ? nd->lo[d] - yt[d] : (yt[d] - nd->hi[d] > 0.0 ? yt[d] - nd->hi[d] : 0.0);
         g2 += gap * gap;
     }
-    if (rc2 <= C->theta * C->theta * R2 && g2 > C->rnear * C->rnear) {
+    if (rc2 <= C->theta * C->theta * R2 && g2 > C->mac_rnear * C->mac_rnear) {
         int np1 = C->p + 1;
         const double *W = C->mw + (size_t)id * np1 * np1 * np1 * 15;
         double su[3] = {0, 0, 0}, sv[3] = {0, 0, 0};
@@ -643,11 +645,12 @@ static void tree_visit(const tree_ctx *C, int id, const double *yt, const double
 }
 
 /* Treecode evaluation of both layers.  out_sl, out_dl: (m,3); optional out_*_delta (m,3,3).
+ * mac_rnear: the radius the MAC requires a cluster's box to lie beyond; <= 0 for the near radius.
  * Returns the number of tree nodes, or -1 if an extrapolation system is singular. */
 int orc_tree(int64_t n, const double *x, const double *nrm, const double *w, const double *f, const double *q,
              int64_t m, const double *y, const double *x0, const double *n0, const double *b, const double *f0,
-             const double *q0, double h, const double rho[3], int p, double theta, int64_t leaf, double *out_sl,
-             double *out_dl, double *out_sl_delta, double *out_dl_delta)
+             const double *q0, double h, const double rho[3], int p, double theta, int64_t leaf, double mac_rnear,
+             double *out_sl, double *out_dl, double *out_sl_delta, double *out_dl_delta)
 {
     orc_tree_t T = {0};
     T.order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -687,7 +690,8 @@ int orc_tree(int64_t n, const double *x, const double *nrm, const double *w, con
     double rmax = rho[0];
     for (int j = 1; j < 3; ++j)
         if (rho[j] > rmax) rmax = rho[j];
-    tree_ctx C = {x, nrm, w, f, q, &T, mw, p, theta, 6.0 * rmax * h, h, {rho[0], rho[1], rho[2]}};
+    tree_ctx C = {x, nrm, w, f, q, &T, mw, p, theta, 6.0 * rmax * h, h, {rho[0], rho[1], rho[2]}, 0.0};
+    C.mac_rnear = mac_rnear > 0.0 ? mac_rnear : C.rnear;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
     for (int64_t it = 0; it < m; ++it) {

@@ -195,6 +195,12 @@ double reach_of(const sr_ctx *c, double radius, double rnear)
     return r;
 }
 
+// The radius the treecode's MAC requires a cluster to lie beyond (launch_tree_far)
+double tree_mac_radius(const sr_ctx *c, double rnear)
+{
+    return c->prm.precision == SR_MIXED ? reach_of(c, rnear, rnear) : rnear;
+}
+
 // Uniform grid of cells of side reach / kCellsPerReach (larger only when the grid would exceed
 // kMaxCells cells); sources sorted by cell with a stable counting sort.
 sr_status build_layout(sr_ctx *c, hipStream_t s)
@@ -721,7 +727,8 @@ sr_status eval_chunk(const char *fn, sr_ctx *c, int layers, int64_t m, const dou
     if (concurrent) SR_HIP(hipEventRecord(c->ev_fork, s));
     if (profile && (st = record_event(c, s)) != SR_OK) return st;
     if (tree) {
-        SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear, dp.rsharp, dp.sharp,
+        SR_HIP(launch_tree_far(c->prm.precision, layers, c->tdev, a, c->prm.tree_theta, dp.rnear,
+                               tree_mac_radius(c, dp.rnear), dp.rsharp, dp.sharp,
                                part, s));
     } else {
         SR_HIP(launch_far_direct(c->prm.precision, layers, c->rec64.p, c->rec32.p, c->n, a, dp.rnear, dp.rsharp,
@@ -985,7 +992,8 @@ sr_status sr_tree_work(sr_ctx *c, int64_t m, const double *y, int64_t *proxy_pai
         return fail(SR_ESTATE, "sr_tree_work: needs far_method SR_TREE and a tree built by a previous sr_eval");
     const std::vector<TreeNode> &nodes = c->tree.nodes;
     const int64_t nprox = (int64_t)(c->tree_p + 1) * (c->tree_p + 1) * (c->tree_p + 1);
-    const double theta2 = c->prm.tree_theta * c->prm.tree_theta, rnear2 = c->grid_rnear * c->grid_rnear;
+    const double theta2 = c->prm.tree_theta * c->prm.tree_theta, mac_r = tree_mac_radius(c, c->grid_rnear),
+                 rnear2 = mac_r * mac_r;
     int64_t np = 0, nl = 0, nc = 0;
     std::vector<int> stack;
     for (int64_t t = 0; t < m; ++t) {

@@ -82,8 +82,11 @@ hipError_t launch_target_order(const double *y, const double *b, int m, const do
 size_t target_sort_tmp_bytes(int m);
 
 // Far field by the treecode into part[split][channel][target], D.nfront splits.
-// rnear / rsharp / sharp: as for launch_far_direct
+// rnear / rsharp / sharp: as for launch_far_direct (the leaf sums' pair test).  mac_rnear: the radius
+// the MAC requires a cluster's box to lie beyond: rnear on the FP64 path, whose pair test is exact to
+// the MAC's; on the mixed path the cell grid's reach (rnear widened by the FP32 rounding of the pair
+// test), so that no source of an accepted cluster is also a near pair of the FP32 test.
 hipError_t launch_tree_far(int precision, int layers, const TreeDev &D, const EvalArgs &a, double theta,
-                           double rnear, double rsharp, int sharp, double *part, hipStream_t s);
+                           double rnear, double mac_rnear, double rsharp, int sharp, double *part, hipStream_t s);
 
 }  // namespace sr

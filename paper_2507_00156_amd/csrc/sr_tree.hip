@@ -682,17 +682,18 @@ size_t target_sort_tmp_bytes(int m)
 }
 
 hipError_t launch_tree_far(int precision, int layers, const TreeDev &D, const EvalArgs &a, double theta,
-                           double rnear, double rsharp, int sharp, double *part, hipStream_t s)
+                           double rnear, double mac_rnear, double rsharp, int sharp, double *part, hipStream_t s)
 {
 #pragma clang fp contract(off)
     const double theta2 = theta * theta, rnear2 = rnear * rnear, rs2 = rsharp * rsharp;
     if (precision == SR_MIXED) {
         const float rc2 = (float)rnear2, rc2s = (float)rs2;
+        const double mac2 = mac_rnear * mac_rnear;
         if (layers == (SR_SL | SR_DL))
-            return launch_far_t<float, true, true>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, rc2s, sharp, part, s);
+            return launch_far_t<float, true, true>(D, D.prox32, D.trec32, a, theta2, mac2, rc2, rc2s, sharp, part, s);
         if (layers == SR_SL)
-            return launch_far_t<float, true, false>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, rc2s, sharp, part, s);
-        return launch_far_t<float, false, true>(D, D.prox32, D.trec32, a, theta2, rnear2, rc2, rc2s, sharp, part, s);
+            return launch_far_t<float, true, false>(D, D.prox32, D.trec32, a, theta2, mac2, rc2, rc2s, sharp, part, s);
+        return launch_far_t<float, false, true>(D, D.prox32, D.trec32, a, theta2, mac2, rc2, rc2s, sharp, part, s);
     }
     if (layers == (SR_SL | SR_DL))
         return launch_far_t<double, true, true>(D, D.prox64, D.trec64, a, theta2, rnear2, rnear2, rs2, sharp, part, s);

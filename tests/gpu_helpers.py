@@ -38,3 +38,17 @@ def gpu_eval(cfg, layers, precision, want_delta=False, idx=None, ev=None):
     if own:
         ev.close()
     return out
+
+
+def tree_mac_radius(cfg, precision, cutoff=6.0):
+    """The radius the library's treecode MAC requires a cluster's box to lie beyond (the tree_theta
+    entry of sr_params in include/stokesreg.h): the near radius on the FP64 path; on the mixed path
+    the near radius widened by the reach of the single-precision pair test."""
+    import numpy as np
+
+    x = np.asarray(cfg["surf"].x, dtype=np.float64)
+    rnear = cutoff * max(cfg["rho"]) * cfg["h"]
+    if precision == 0:
+        return rnear
+    ext = max(0.5 * (float(x[:, d].max()) - float(x[:, d].min())) for d in range(3))
+    return rnear * (1.0 + 1e-5) + 4.0 * 2.0 ** -24 * (2.0 * ext + rnear)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workload
-from tests.gpu_helpers import gpu_eval, rel_err, to_dev
+from tests.gpu_helpers import gpu_eval, rel_err, to_dev, tree_mac_radius
 
 pytestmark = pytest.mark.gpu
 
@@ -56,7 +56,7 @@ def small():
 def test_tree_matches_oracle_tree(P, small, precision, p, theta, leaf):
     cfg = small
     gu, gv = tree_eval(P, cfg, precision, p, theta, leaf)
-    ou, ov = oracle.tree_cfg(cfg, None, p=p, theta=theta, leaf=leaf)
+    ou, ov = oracle.tree_cfg(cfg, None, p=p, theta=theta, leaf=leaf, mac_rnear=tree_mac_radius(cfg, precision))
     e1, e2 = rel_err(gu, ou), rel_err(gv, ov)
     print(f"tree p={p} theta={theta} leaf={leaf} prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
     assert e1 <= TOL[precision] and e2 <= TOL[precision]
@@ -116,7 +116,7 @@ def test_tree_c3_sampled(P):
     rng = np.random.default_rng(7)
     idx = np.concatenate([rng.choice(n, 80, replace=False), n + rng.choice(t.m - n, 80, replace=False)])
     gu, gv = tree_eval(P, cfg, 1, 8, 0.7, 2000)
-    ou, ov = oracle.tree_cfg(cfg, idx, p=8, theta=0.7, leaf=2000)
+    ou, ov = oracle.tree_cfg(cfg, idx, p=8, theta=0.7, leaf=2000, mac_rnear=tree_mac_radius(cfg, 1))
     e1, e2 = rel_err(gu[idx], ou), rel_err(gv[idx], ov)
     print(f"c3 tree mixed: SL {e1:.3e} DL {e2:.3e}", flush=True)
     assert e1 <= 1e-7 and e2 <= 1e-7
@@ -126,7 +126,7 @@ def _count_tree_work(x, y, leaf, p, theta, rnear):
     """Independent count of the treecode work: the octree of section 3.4 (midpoint split into 8
     octants, upper half when x >= mid, empty octants dropped, boxes the bounding boxes of their
     points, no split when all points fall in one octant) and the MAC r_c^2 <= theta^2 R^2 with the
-    box farther than the near radius, in FP64 operation by operation."""
+    box farther than rnear (the MAC's near radius), in FP64 operation by operation."""
     nodes = []
 
     def build(idx):
@@ -189,8 +189,7 @@ def test_tree_work_counts(P, small, p, theta, leaf):
             to_dev(cfg["q0"]))
     npx, nlf, ncl = ev.tree_work(t.y)
     ev.close()
-    rnear = 6.0 * max(cfg["rho"]) * cfg["h"]
-    ref = _count_tree_work(s.x, t.y, leaf, p, theta, rnear)
+    ref = _count_tree_work(s.x, t.y, leaf, p, theta, tree_mac_radius(cfg, 1))
     print(f"tree work p={p} theta={theta} leaf={leaf}: proxy {npx} leaf {nlf} clustered {ncl}", flush=True)
     assert (npx, nlf, ncl) == ref
     assert ncl + nlf == t.m * s.n
@@ -213,7 +212,7 @@ def test_tree_sweep_configurations_match_oracle(P, spheroid128, precision, p, th
     rng = np.random.default_rng(p * 1000 + leaf + int(theta * 10))
     idx = np.sort(rng.choice(cfg["targets"].m, 150, replace=False))
     gu, gv = tree_eval(P, cfg, precision, p, theta, leaf, idx)
-    ou, ov = oracle.tree_cfg(cfg, idx, p=p, theta=theta, leaf=leaf)
+    ou, ov = oracle.tree_cfg(cfg, idx, p=p, theta=theta, leaf=leaf, mac_rnear=tree_mac_radius(cfg, precision))
     e1, e2 = rel_err(gu, ou), rel_err(gv, ov)
     print(f"sweep config p={p} theta={theta} N0={leaf} prec={precision}: SL {e1:.3e} DL {e2:.3e}", flush=True)
     assert e1 <= TOL[precision] and e2 <= TOL[precision]

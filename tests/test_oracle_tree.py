@@ -54,3 +54,18 @@ def test_single_leaf_is_direct(small):
     cfg, idx, u, v = small
     tu, tv = oracle.tree_cfg(cfg, idx, p=3, theta=0.7, leaf=10 ** 7)
     assert _err(tu, u) < 1e-12 and _err(tv, v) < 1e-12
+
+
+def test_mac_radius_beyond_the_surface_is_direct(small):
+    """A MAC radius larger than the surface's diameter accepts no cluster, whatever theta: the treecode
+    is then the direct sum; a radius between the two moves only some clusters to the leaf sums, so the
+    error lies between the paper's MAC's and zero."""
+    cfg, idx, u, v = small
+    x = cfg["surf"].x
+    diam = float(np.linalg.norm(x.max(0) - x.min(0)))
+    tu, tv = oracle.tree_cfg(cfg, idx, p=4, theta=0.9, leaf=100, mac_rnear=2.0 * diam)
+    assert _err(tu, u) < 1e-12 and _err(tv, v) < 1e-12
+    rnear = 6.0 * max(cfg["rho"]) * cfg["h"]
+    e_paper = _err(oracle.tree_cfg(cfg, idx, p=4, theta=0.9, leaf=100)[0], u)
+    e_wide = _err(oracle.tree_cfg(cfg, idx, p=4, theta=0.9, leaf=100, mac_rnear=2.0 * rnear)[0], u)
+    assert e_wide < e_paper
