@@ -901,7 +901,7 @@ sr_status sr_rigid_solve_refined(sr_rigid *R, const double *rhs, double *x, int 
     if (R->ctx64.empty()) {
         sr_params p64 = R->prm;
         p64.precision = SR_FP64;
-        p64.far_method = SR_DIRECT;  // the judge of the residual is the exact operator, whatever the inner one
+        p64.far_method = SR_DIRECT;  // the residual is measured with the exact operator, whatever the inner one
         for (int m = 0; m < R->nsph; ++m) {
             sr_ctx *c = nullptr;
             RSR(sr_create(&c, R->device));
