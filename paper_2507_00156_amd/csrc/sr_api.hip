@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -67,6 +68,37 @@ struct DevBuf {
 };
 
 bool is_pos_finite(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Host smoothing tables by parameter set (rho, cutoff, range), shared by the contexts of the process:
+// building and checking one takes tens of milliseconds on the host, and the rigid-sphere solve makes
+// new contexts with the same parameters for every new geometry.  Failed checks are kept as well.
+struct NearTableEntry {
+    double key[5];
+    bool ok;
+    std::vector<double> tab;
+};
+std::mutex g_tab_mu;
+std::vector<NearTableEntry> g_tab_cache;
+constexpr size_t kTabCacheMax = 32;
+
+bool near_table_cached(const double key[5], const double rho[3], double cutoff, double X, std::vector<double> &out)
+{
+    std::lock_guard<std::mutex> lock(g_tab_mu);
+    for (const NearTableEntry &e : g_tab_cache)
+        if (std::equal(key, key + 5, e.key)) {
+            out = e.tab;
+            return e.ok;
+        }
+    NearTableEntry e;
+    std::copy(key, key + 5, e.key);
+    double err = 0.0;
+    e.ok = build_near_table(rho, cutoff, X, e.tab, &err);
+    out = e.tab;
+    const bool ok = e.ok;
+    if (g_tab_cache.size() >= kTabCacheMax) g_tab_cache.erase(g_tab_cache.begin());
+    g_tab_cache.push_back(std::move(e));
+    return ok;
+}
 
 }  // namespace
 
@@ -636,8 +668,7 @@ sr_status eval_chunk(const char *fn, sr_ctx *c, int layers, int64_t m, const dou
         const double key[5] = {dp.rho[0], dp.rho[1], dp.rho[2], dp.cutoff, X};
         const bool same = std::equal(key, key + 5, c->tab_key);
         if (!same && !noalloc) {
-            double err = 0.0;
-            c->tab_ok = build_near_table(dp.rho, dp.cutoff, X, c->near_tab_host, &err);
+            c->tab_ok = near_table_cached(key, dp.rho, dp.cutoff, X, c->near_tab_host);
             std::copy(key, key + 5, c->tab_key);
             if (c->tab_ok) {
                 // synchronized: the host copy may be rebuilt by the next call with other parameters
