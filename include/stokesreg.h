@@ -183,8 +183,8 @@ int64_t sr_max_targets(void);
  *           the table against long-double evaluations, at 17 points per interval, relative to the
  *           function's largest value.
  * sr_eval builds it with xmax = cutoff max(rho) (1 + 1e-5) (the near radius over h, widened for the
- * rounding of the pair test), once per parameter set, when neither per-delta outputs nor the modified
- * smoothing are asked for.
+ * rounding of the pair test), once per parameter set and process, when neither per-delta outputs
+ * nor the modified smoothing are asked for.
  * SR_EINVAL for NULL rho or tab, n too small, or a parameter out of range; SR_ENOCONV if the checked
  * error exceeds 5e-14 (tab is then left unchanged; sr_eval uses the closed forms for such
  * parameters).  Host only: needs no GPU. */
