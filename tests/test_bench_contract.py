@@ -20,3 +20,21 @@ def test_recorded_far_traffic_belongs_to_the_committed_kernel():
     import bench
 
     assert bench.far_traffic("fp64") is not None and bench.far_traffic("mixed") is not None
+
+
+def test_near_pair_count_equals_brute_force():
+    """The roofline's far-pair count is M N less the pairs within the near radius; the k-d tree count
+    behind it equals a direct count over every pair (small workload)."""
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import workload
+
+    cfg = workload.build_config("small")
+    x, y = cfg["surf"].x, cfg["targets"].y
+    rnear = 6.0 * max(cfg["rho"]) * cfg["h"]
+    d2 = ((y[:, None, :] - x[None, :, :]) ** 2).sum(-1)
+    assert bench.near_pair_count(cfg) == int((d2 <= rnear * rnear).sum())
+    # 34 flops per far single-layer pair and 32 per double-layer pair
+    assert bench.FAR_FLOPS_PER_PAIR_SLDL == 66
